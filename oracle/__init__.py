@@ -1,0 +1,46 @@
+"""FP64 CPU oracle for the iterative Fourier-transform hologram path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+path (no kernels, tables, constants or helpers) and imports nothing from it.
+
+What it computes, and where it comes from.  The paper (Structure and Design of
+HoloGen) names the algorithms and primitives of its CUDA backend -- the cuFFT
+wrapper, the quantiser, the normaliser, the randomiser, Gerchberg-Saxton and
+One-Step Phase-Retrieval (Sec. 7.3, Algorithm Libraries), Fourier and Fresnel
+holograms (Abstract keywords) -- but prints no formula.  Each module therefore
+writes out the textbook definition the paper presupposes, in FP64/complex128,
+step by step in the order the method performs it:
+
+  dft.py          discrete Fourier transform: a naive O(N^2) DFT and the
+                  oracle's own recursive mixed-radix Cooley-Tukey FFT
+                  (Cooley & Tukey 1965), 2D as rows then columns.
+  optics.py       Fourier and single-FFT Fresnel propagation (Goodman,
+                  Introduction to Fourier Optics, Fresnel diffraction).
+  constraints.py  SLM-plane phase-only projection, uniform L-level phase
+                  quantiser, binary-phase binariser, replay-plane amplitude
+                  replacement.
+  metrics.py      energy-normalised NMSE of an intensity against a target.
+  gs.py           Gerchberg-Saxton error-reduction iteration (Gerchberg &
+                  Saxton 1972; Fienup 1982).
+  ospr.py         One-Step Phase-Retrieval (Cable, Buckley et al. 2004).
+
+Readings taken where the paper is silent are listed in the design doc.  Every
+function is pinned by ``tests/test_oracle_*.py`` against closed forms,
+brute-force sums, invariants and independent library routines.
+"""
+from .dft import dft_naive, fft, ifft, fft2, ifft2, fftshift, ifftshift
+from .optics import fresnel_chirp, fresnel_geometry, propagate
+from .constraints import (quantise_level, quantise_phase_level, phase_only,
+                          replace_amplitude, binarise)
+from .metrics import nmse
+from .gs import gs_iterate
+from .ospr import ospr
+
+__all__ = [
+    "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
+    "fresnel_chirp", "fresnel_geometry", "propagate",
+    "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
+    "binarise", "nmse", "gs_iterate", "ospr",
+]

@@ -1,0 +1,102 @@
+"""Gerchberg-Saxton error-reduction iteration (FP64).
+
+Test infrastructure only.  The paper's HoloGenAlgGSCuda implements
+"Gerchberg-Saxton and other iterative Fourier transform approaches" in the
+RunIterations() function of an algorithm object that holds the target,
+illumination and starting images (Sec. 4, Algorithm Interface; Sec. 7.3).  The
+update rule is the textbook one (Gerchberg & Saxton, Optik 35, 1972; Fienup,
+Appl. Opt. 21, 1982, error-reduction form):
+
+  T_f   = ifftshift(T_amp)                 target amplitude in FFT order
+  H_0   = A * exp(i C(phi_0))              C = identity, or the quantiser
+  for k = 0 .. n:
+      R_k  = FFT2(Q1 * H_k)                replay field (Q1 = 1 for Fourier)
+      nmse[k] = NMSE(|R_k|^2, T_f^2)
+      stop if k == n
+      R'_k = T_f * R_k / |R_k|             impose the target amplitude
+      G_k  = conj(Q1) * IFFT2(R'_k)        back to the SLM plane
+      H_{k+1} = A * P(G_k)                 P = phase-only projection or the
+                                           L-level quantiser
+  phi_n = mod(arg P(G_{n-1}), 2 pi)        (the constrained phi_0 when n = 0)
+
+Q1 is the source chirp of the single-FFT Fresnel transform.  The output chirp,
+the prefactor and the centring permutations of the full Fresnel operator are a
+unit-modulus replay-plane factor and a permutation: amplitude replacement keeps
+them and the inverse removes them, so the loop above reproduces the physical
+Fresnel loop exactly (tests/test_oracle_gs.py checks this against optics.py).
+
+The Fienup error E_k = sum (|R_k| - c T_f)^2, c^2 = N_px sum A^2 / sum T_f^2,
+is returned on request; for this nearest-point (error-reduction) iteration it
+never increases (Fienup 1982).
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from .dft import fft2, ifft2, ifftshift
+from .optics import fresnel_chirp
+from .constraints import quantise_level, quantise_phase_level, phase_only, replace_amplitude
+from .metrics import nmse as nmse_fn
+
+TWO_PI = 2.0 * np.pi
+
+
+def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
+               levels: int = 0, illumination: Optional[np.ndarray] = None,
+               fresnel: Optional[dict] = None, fienup: bool = False) -> dict:
+    """Run GS from phi0.
+
+    target_amp, phi0: [H][W] real arrays (target in centred order, phase in SLM
+    order).  levels: 0 for a continuous phase-only SLM, else L >= 2.
+    fresnel: None for a Fourier hologram, else a dict with keys wavelength,
+    pitch, distance (metres).  Returns phase [H][W] in [0, 2pi), levels
+    [H][W] int64 (or None), nmse list of length iterations+1 and optionally the
+    Fienup errors.
+    """
+    t_amp = np.asarray(target_amp, dtype=np.float64)
+    h, w = t_amp.shape
+    t_f = ifftshift(t_amp)
+    t_int = t_f * t_f
+    amp = np.ones((h, w)) if illumination is None else np.asarray(illumination, np.float64)
+    if fresnel is None:
+        q1 = np.ones((h, w), dtype=np.complex128)
+    else:
+        q1 = np.outer(fresnel_chirp(h, fresnel["pitch"], fresnel["wavelength"], fresnel["distance"]),
+                      fresnel_chirp(w, fresnel["pitch"], fresnel["wavelength"], fresnel["distance"]))
+
+    phi0 = np.asarray(phi0, dtype=np.float64)
+    if levels:
+        lev = quantise_phase_level(phi0, levels)
+        unit = np.exp(1j * lev * (TWO_PI / levels))
+    else:
+        lev = None
+        unit = np.exp(1j * phi0)
+    slm = amp * unit
+
+    c_scale = np.sqrt(h * w * np.sum(amp * amp) / np.sum(t_f * t_f))
+    errors, fienup_err = [], []
+    for k in range(iterations + 1):
+        replay = fft2(q1 * slm)
+        errors.append(nmse_fn(np.abs(replay) ** 2, t_int))
+        if fienup:
+            fienup_err.append(float(np.sum((np.abs(replay) - c_scale * t_f) ** 2)))
+        if k == iterations:
+            break
+        back = np.conj(q1) * ifft2(replace_amplitude(replay, t_f))
+        if levels:
+            lev = quantise_level(back, levels)
+            unit = np.exp(1j * lev * (TWO_PI / levels))
+        else:
+            unit = phase_only(back)
+        slm = amp * unit
+
+    if levels:
+        phase = lev * (TWO_PI / levels)
+    else:
+        phase = np.mod(np.arctan2(unit.imag, unit.real), TWO_PI)
+    out = {"phase": phase, "levels": lev, "nmse": errors}
+    if fienup:
+        out["fienup"] = fienup_err
+    return out
