@@ -1,0 +1,181 @@
+"""Throughput of the Gerchberg-Saxton hot path on one MI355X.
+
+Workload: Fresnel GS hologram, 1024x1024 complex FP32 field, 8-level phase
+quantisation, 100 iterations per step (lambda 532 nm, 8 um pitch, z 0.5 m;
+synthetic target seed 2, starting phase seed 3).  One step = one
+hg_gs_iterate call: per-call statistics, the start row pass, 100 x (replay
+column pass + SLM row pass), the final NMSE pass and the NMSE reduction.
+Successive steps continue from the SLM state the previous step left, which
+is the same work per step.
+
+Output: one JSON line with iterations/s, the roofline position of the
+dominant kernel (HIP events on the launch stream) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GS iterations/s at 1024² (HBM GB/s, % peak); grad-CGH vs GS time to NMSE"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per pixel of one launch: field read + target read + field write
+BYTES_PER_PX = {"gs_replay_column_pass": 8 + 4 + 8, "gs_slm_row_pass": 8 + 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2006_10509_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    entry = data.get(kernel)
+    if not entry or entry.get("source_hash") != source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, target, phi0, sample_iters: int):
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    fres = dict(wavelength=workload.wavelength, pitch=workload.pitch, distance=workload.distance)
+    t0 = time.perf_counter()
+    oracle.gs_iterate(target, phi0, sample_iters, levels=workload.levels, fresnel=fres)
+    dt = time.perf_counter() - t0
+    return {"value": sample_iters / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{sample_iters} of the {workload.iterations} iterations of the same "
+                      f"{workload.height}x{workload.width} workload and inputs, FP64, "
+                      f"including its one extra NMSE transform ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part "
+              "of this build", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2006_10509_amd import hologen as hg
+    from paper_2006_10509_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        return 1
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1024 * 1024, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": src.numel() * 8,
+                          "bytes_written_per_dispatch": dst.numel() * 8, "dispatches": 20}))
+        return 0
+    w = wl.GS_FRESNEL_1024
+    target, phi0 = w.inputs()
+    plan = hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, w.distance,
+                   hg.HG_PHASE_QUANTISED, w.levels)
+    t = torch.from_numpy(target).cuda()
+    phase = torch.from_numpy(phi0.copy()).cuda()
+    levels = torch.empty((w.height, w.width), dtype=torch.uint8, device="cuda")
+    nmse = torch.empty(w.iterations + 1, dtype=torch.float32, device="cuda")
+    ws = plan.workspace()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        hg.hg_gs_iterate(plan, t, phase, w.iterations, ws, levels=levels, nmse=nmse, stream=stream)
+
+    log(f"warmup {args.warmup} steps of {w.name}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    first_nmse = float(nmse[-1].item())
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = w.iterations * args.steps / elapsed
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.0f} iterations/s, "
+        f"final NMSE {first_nmse:.6f}")
+
+    # per-kernel durations with HIP events on the launch stream
+    kstats = {}
+    for name, kid in (("gs_replay_column_pass", hg.HG_KERNEL_GS_REPLAY), ("gs_slm_row_pass", hg.HG_KERNEL_GS_SLM)):
+        hg.hg_timing_begin(plan, kid)
+        for _ in range(max(3, args.steps // 5)):
+            step()
+        total_ms, count = hg.hg_timing_end(plan)
+        kstats[name] = total_ms / max(count, 1)
+        log(f"{name}: {kstats[name] * 1e3:.2f} us/launch over {count} launches")
+    dominant = max(kstats, key=kstats.get)
+    npx = w.height * w.width
+    alg_bytes = BYTES_PER_PX[dominant] * npx
+    achieved = alg_bytes / (kstats[dominant] * 1e-3) / 1e9
+    iter_gbs = sum(BYTES_PER_PX.values()) * npx * value / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
+                "kernel": dominant, "us_per_launch": round(kstats[dominant] * 1e3, 3),
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "iteration_gbs": round(iter_gbs, 1), "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_sample_iters} iterations")
+        cpu = cpu_baseline(w, target, phi0, args.cpu_sample_iters)
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "iterations/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w.name, "height": w.height, "width": w.width,
+                      "iterations_per_step": w.iterations, "levels": w.levels, "propagation": "fresnel",
+                      "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
+                      "target_seed": w.target_seed, "phase_seed": w.phase_seed},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,169 @@
+/*
+ * hologen.h -- C ABI of the MI355X (gfx950) iterative Fourier-transform
+ * hologram library: Gerchberg-Saxton and One-Step Phase-Retrieval holograms,
+ * Fourier or Fresnel, phase-only, multi-level or binary SLMs.
+ *
+ * The calls follow the way the paper's algorithm objects receive a problem:
+ * an algorithm object stores the target, illumination and starting images and
+ * the common parameters, moves them to the GPU, and runs the iterations in
+ * RunIterations() (Sec. 4, Algorithm Interface; Sec. 7.3, AlgorithmCuda).  The
+ * plan descriptor carries the SLM resolution and type (Sec. 3.2, the
+ * SLMResolutionX / SLMTypeOption / MultiAmpSLM options), the Fourier or
+ * Fresnel propagation (Abstract keywords) and the quantiser levels (Sec. 7.3,
+ * QuantiserCuda).
+ *
+ * Conventions shared by every call
+ *   - Arrays are row-major [height][width]; width is the contiguous axis.
+ *   - Complex arrays are interleaved complex64 (float re, float im).
+ *   - SLM-plane arrays (phase, levels, illumination) are in natural pixel
+ *     order.  Replay-plane arrays (targets, OSPR subframe phases, OSPR
+ *     intensity, Fresnel output fields) are in centred image order: the
+ *     optical axis sits at (height/2, width/2) (integer division).
+ *   - Forward transform: X[k] = sum_n x[n] exp(-2 pi i n k / N), unnormalised;
+ *     inverse: exp(+2 pi i n k / N) scaled by 1/N.  2D = rows then columns.
+ *   - Every pointer argument except the plan descriptor and out-parameters is
+ *     a DEVICE pointer owned by the caller; the library never frees it.  The
+ *     plan owns only small tables (twiddles, chirps, level values).
+ *   - Calls validate all host-visible arguments first and return a status
+ *     without enqueueing anything when validation fails.  On success the work
+ *     is enqueued on `stream` (0 = the null stream) and the results are valid
+ *     once the stream has been synchronised.  Launch failures return
+ *     HG_ERR_DEVICE; hg_error() then gives the HIP error text.
+ *   - A plan is immutable after creation and may be used from several host
+ *     threads and streams at once if every concurrent call has its own
+ *     workspace.  Using a plan after hg_plan_destroy is undefined.
+ */
+#ifndef HOLOGEN_H
+#define HOLOGEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hg_plan_s* hg_plan;
+
+typedef enum {
+  HG_OK = 0,
+  HG_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad enum, non-finite optics, ... */
+  HG_ERR_UNSUPPORTED_SIZE = 2, /* a dimension this build has no transform for   */
+  HG_ERR_OUT_OF_MEMORY = 3,    /* plan tables could not be allocated            */
+  HG_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed            */
+  HG_ERR_INTERNAL = 5
+} hg_status;
+
+enum { HG_FOURIER = 0, HG_FRESNEL = 1 };                               /* propagation */
+enum { HG_PHASE = 0, HG_PHASE_QUANTISED = 1, HG_BINARY_PHASE = 2 };   /* SLM modulation */
+enum { HG_FORWARD = 1 /* SLM -> replay */, HG_INVERSE = -1 /* replay -> SLM */ };
+
+typedef struct {
+  int32_t width, height;   /* SLM resolution in pixels; each must be a compiled
+                              transform length (hg_length_supported)            */
+  int32_t propagation;     /* HG_FOURIER or HG_FRESNEL                           */
+  double wavelength;       /* metres; Fresnel only: finite and > 0               */
+  double pixel_pitch;      /* metres; Fresnel only: finite and > 0               */
+  double distance;         /* metres; Fresnel only: finite and > 0               */
+  int32_t modulation;      /* HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE    */
+  int32_t levels;          /* 0 for HG_PHASE; 2..256 for HG_PHASE_QUANTISED;
+                              2 for HG_BINARY_PHASE                              */
+} hg_plan_desc;
+
+/* Create a plan on the current HIP device: validates the descriptor, builds
+ * the FP64 twiddle, chirp and level tables, rounds them to FP32 and copies
+ * them to the device (synchronously).  *out is set only on HG_OK. */
+hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out);
+
+/* Free the plan's device tables.  The caller must make sure no enqueued work
+ * still uses the plan.  NULL is accepted and ignored. */
+hg_status hg_plan_destroy(hg_plan plan);
+
+/* Bytes of device workspace every hg_propagate / hg_gs_iterate / hg_ospr call
+ * on this plan needs (a complex64 field plus reduction scratch).  0 for NULL. */
+size_t hg_workspace_bytes(hg_plan plan);
+
+/* 1 if this build compiles a transform of length n (usable as a width or a
+ * height), else 0. */
+int32_t hg_length_supported(int32_t n);
+
+/* Propagate one complex64 field between the SLM and replay planes.
+ *   HG_FOURIER: forward = 2D FFT, inverse = 2D inverse FFT (x 1/(H W)); both
+ *               in FFT index order (the raw transform).
+ *   HG_FRESNEL: the single-FFT Fresnel transform and its exact inverse:
+ *       U_z = c Q2 fftshift(FFT2(ifftshift(Q1 U_0))),
+ *       Q1 = exp(i pi (xi^2 + eta^2)/(lambda z)) at xi = (n - W/2) p,
+ *       Q2 = exp(i pi (x^2 + y^2)/(lambda z)) at x = (k - W/2) lambda z/(W p),
+ *       c  = exp(i 2 pi z / lambda) / (i lambda z) * p^2;
+ *     SLM field in natural order, replay field in centred order.
+ * in and out may be the same buffer.  workspace may be NULL (unused). */
+hg_status hg_propagate(hg_plan plan, const void* in_c64, void* out_c64, int32_t direction,
+                       void* workspace, hipStream_t stream);
+
+/* Gerchberg-Saxton error reduction (Sec. 7.3, HoloGenAlgGSCuda):
+ *   T_f = ifftshift(target_amp);  H_0 = A exp(i C(phase_in))
+ *   for k = 0..iterations:
+ *     R_k = FFT2(Q1 H_k)            (Q1 = 1 for HG_FOURIER, the source chirp
+ *                                    above for HG_FRESNEL)
+ *     nmse[k] = NMSE(|R_k|^2, T_f^2); stop at k = iterations
+ *     H_{k+1} = A P(conj(Q1) IFFT2(T_f R_k / |R_k|))
+ * with P = phase-only projection G/|G| (HG_PHASE) or the uniform quantiser
+ * l = floor(mod(arg G, 2 pi) L / (2 pi) + 1/2) mod L, value exp(2 pi i l / L)
+ * (HG_PHASE_QUANTISED, and HG_BINARY_PHASE with L = 2); C is the identity or
+ * the same quantiser applied to the starting phase.
+ *   NMSE(I, T) = sum (I/sum I - T/sum T)^2 / sum (T/sum T)^2, full frame, with
+ *   sum I = H W sum A^2 (Parseval).
+ * target_amp   [H][W] float, centred, >= 0, not all zero.      (required)
+ * illumination [H][W] float SLM amplitude A; NULL means A = 1.
+ * phase        [H][W] float: in = starting phase (radians, finite), out =
+ *              phase of H_iterations in [0, 2 pi).             (required)
+ * levels       [H][W] uint8 level index of H_iterations (0 in HG_PHASE mode);
+ *              NULL to skip.
+ * nmse         [iterations + 1] float; NULL to skip the error metric.
+ * iterations   >= 0.
+ * workspace    hg_workspace_bytes(plan) bytes of device memory.  (required) */
+hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illumination, float* phase,
+                        uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                        hipStream_t stream);
+
+/* One-Step Phase-Retrieval, binary phase (Sec. 7.3, HoloGenAlgOSPRCuda), on a
+ * HG_FOURIER plan:
+ *   for n < n_sub: G_n = IFFT2(ifftshift(target_amp exp(i sub_phase[n])));
+ *                  h_n = +1 (level 0) if Re G_n >= 0 else -1 (level 1);
+ *                  I_n = |FFT2(h_n)|^2
+ *   intensity = fftshift(mean_n I_n),  nmse[0] = NMSE(intensity, target_amp^2).
+ * target_amp [H][W] float centred (required); sub_phase [n_sub][H][W] float
+ * centred (required); holograms [n_sub][H][W] uint8 levels or NULL; intensity
+ * [H][W] float centred (required); nmse [1] float or NULL; n_sub >= 1. */
+hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_sub,
+                  uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
+
+/* Diagnostics: per-kernel timing with HIP events.
+ * hg_timing_begin makes every later launch of `kernel` made by calls on this
+ * plan record a hipEvent before and after it on the call's stream;
+ * hg_timing_end waits for the last of those events, returns the summed
+ * kernel time and the number of timed launches, and switches timing off.
+ * The events sit between launches, so they add a small gap of their own;
+ * time the plain calls separately for throughput.  A plan in timing mode
+ * must be used from one host thread.
+ * kernel: HG_KERNEL_GS_REPLAY (column pass of GS: FFT, NMSE, amplitude
+ * replacement, inverse FFT), HG_KERNEL_GS_SLM (row pass of GS: inverse FFT,
+ * SLM constraint, FFT), HG_KERNEL_OSPR_A / _B / _C (the three OSPR passes),
+ * HG_KERNEL_PROP_ROW / _COL (hg_propagate passes). */
+enum { HG_KERNEL_GS_REPLAY = 1, HG_KERNEL_GS_SLM = 2, HG_KERNEL_OSPR_A = 3, HG_KERNEL_OSPR_B = 4,
+       HG_KERNEL_OSPR_C = 5, HG_KERNEL_PROP_ROW = 6, HG_KERNEL_PROP_COL = 7 };
+hg_status hg_timing_begin(hg_plan plan, int32_t kernel);
+hg_status hg_timing_end(hg_plan plan, double* total_ms, int64_t* launches);
+
+/* Static text for a status.  If s equals the calling thread's last non-OK
+ * status, the text also carries that call's detail (argument name, HIP
+ * error).  Never NULL; the pointer stays valid until this thread's next
+ * library call. */
+const char* hg_error(hg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOLOGEN_H */

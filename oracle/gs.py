@@ -45,7 +45,8 @@ TWO_PI = 2.0 * np.pi
 
 def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
                levels: int = 0, illumination: Optional[np.ndarray] = None,
-               fresnel: Optional[dict] = None, fienup: bool = False) -> dict:
+               fresnel: Optional[dict] = None, fienup: bool = False,
+               return_back: bool = False, trace: bool = False) -> dict:
     """Run GS from phi0.
 
     target_amp, phi0: [H][W] real arrays (target in centred order, phase in SLM
@@ -53,7 +54,11 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
     fresnel: None for a Fourier hologram, else a dict with keys wavelength,
     pitch, distance (metres).  Returns phase [H][W] in [0, 2pi), levels
     [H][W] int64 (or None), nmse list of length iterations+1 and optionally the
-    Fienup errors.
+    Fienup errors.  return_back adds the last back-propagated field G_{n-1}
+    (None when n = 0), from which a caller can tell how close each quantiser
+    decision was to a level boundary.  trace (quantised mode) adds, for every
+    state k = 0..n, the levels of H_k and the angle that was quantised to get
+    them (phi_0 for k = 0, arg G_{k-1} after that).
     """
     t_amp = np.asarray(target_amp, dtype=np.float64)
     h, w = t_amp.shape
@@ -74,9 +79,13 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
         lev = None
         unit = np.exp(1j * phi0)
     slm = amp * unit
+    states = []
+    if trace and levels:
+        states.append({"levels": lev.astype(np.uint8), "angle": phi0.copy()})
 
     c_scale = np.sqrt(h * w * np.sum(amp * amp) / np.sum(t_f * t_f))
     errors, fienup_err = [], []
+    back = None
     for k in range(iterations + 1):
         replay = fft2(q1 * slm)
         errors.append(nmse_fn(np.abs(replay) ** 2, t_int))
@@ -88,6 +97,8 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
         if levels:
             lev = quantise_level(back, levels)
             unit = np.exp(1j * lev * (TWO_PI / levels))
+            if trace:
+                states.append({"levels": lev.astype(np.uint8), "angle": np.angle(back)})
         else:
             unit = phase_only(back)
         slm = amp * unit
@@ -99,4 +110,8 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
     out = {"phase": phase, "levels": lev, "nmse": errors}
     if fienup:
         out["fienup"] = fienup_err
+    if return_back:
+        out["back"] = back
+    if trace and levels:
+        out["trace"] = states
     return out

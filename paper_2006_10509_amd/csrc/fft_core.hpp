@@ -1,0 +1,393 @@
+// Device building blocks of the Stockham autosort FFT used by every pass.
+//
+// The paper delegates its transforms to cuFFT behind FFTHandlerCuda (Sec. 2;
+// Sec. 7.3).  Here the transform is written out for gfx950: one transform of
+// length N is carried by a team of T threads; each thread holds its share of
+// the sequence in registers, every radix-R stage is a set of R-point DFTs done
+// in registers, and the data moves between stages through LDS in Stockham
+// (self-sorting) order, so no bit-reversal pass exists.  Twiddles come from a
+// table exp(-2 pi i m / N) that the host builds in FP64 and rounds to FP32;
+// each thread copies the few entries its butterflies need into registers once
+// per kernel, before the field arrives, so no table access sits between
+// stages.
+//
+// Stage s with radix R and Ns = product of the radices before it: butterfly j
+// (0 <= j < N/R) takes x[j + r N/R], r < R, multiplies by w^(r k) with
+// k = j mod Ns and w = exp(-+2 pi i / (Ns R)), does an R-point DFT and writes
+// output r to (j - k) R + k + r Ns (Stockham 1966; Van Loan 1992, Sec. 1.7).
+// Butterflies are dealt to the team's threads round-robin: thread t takes
+// j = t + m T.  The first stage therefore reads x[t + m T + r N/R0] and the last
+// stage leaves X[t + m T + r N/R_last] in registers, both unit-stride across
+// threads, so the global loads and stores around a transform coalesce.
+// Running the radices in reversed order leaves the layout the forward order
+// starts from, which lets a kernel chain an inverse and a forward transform
+// (or the reverse) with a pointwise step between them and no extra exchange.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hg {
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2: .x real, .y imaginary)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulconj(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// multiply by DIR * i  (DIR = -1: forward kernel exp(-...), +1: inverse)
+template <int DIR> __device__ __forceinline__ float2 mul_dir_i(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// exact constants of the small DFTs
+#define HG_SQRT1_2 0.70710678118654752440f
+#define HG_COS_PI_8 0.92387953251128675613f
+#define HG_SIN_PI_8 0.38268343236508977173f
+#define HG_SIN_PI_3 0.86602540378443864676f
+#define HG_COS_2PI_5 0.30901699437494742410f
+#define HG_COS_4PI_5 (-0.80901699437494742410f)
+#define HG_SIN_2PI_5 0.95105651629515357212f
+#define HG_SIN_4PI_5 0.58778525229247312917f
+
+// ---------------------------------------------------------------------------
+// R-point DFTs in registers, natural order in and out
+// ---------------------------------------------------------------------------
+template <int DIR> __device__ __forceinline__ void dft2(float2* a) {
+  float2 t = a[1];
+  a[1] = csub(a[0], t);
+  a[0] = cadd(a[0], t);
+}
+
+template <int DIR> __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mul_dir_i<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int DIR> __device__ __forceinline__ void dft4(float2* a) { dft4<DIR>(a[0], a[1], a[2], a[3]); }
+
+// w8^1 and w8^3 with w8 = exp(DIR 2 pi i / 8)
+template <int DIR> __device__ __forceinline__ float2 mul_w8_1(float2 a) {
+  return DIR < 0 ? make_float2(HG_SQRT1_2 * (a.x + a.y), HG_SQRT1_2 * (a.y - a.x))
+                 : make_float2(HG_SQRT1_2 * (a.x - a.y), HG_SQRT1_2 * (a.x + a.y));
+}
+template <int DIR> __device__ __forceinline__ float2 mul_w8_3(float2 a) {
+  return DIR < 0 ? make_float2(HG_SQRT1_2 * (a.y - a.x), -HG_SQRT1_2 * (a.x + a.y))
+                 : make_float2(-HG_SQRT1_2 * (a.x + a.y), HG_SQRT1_2 * (a.x - a.y));
+}
+
+template <int DIR> __device__ __forceinline__ void dft8(float2* a) {
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  o1 = mul_w8_1<DIR>(o1);
+  o2 = mul_dir_i<DIR>(o2);
+  o3 = mul_w8_3<DIR>(o3);
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+
+// w16^m, m in {1,2,3,4,6,9}
+template <int DIR, int M> __device__ __forceinline__ float2 mul_w16(float2 a) {
+  constexpr float s = (float)DIR;
+  if constexpr (M == 0) return a;
+  else if constexpr (M == 1) return cmul(a, make_float2(HG_COS_PI_8, s * HG_SIN_PI_8));
+  else if constexpr (M == 2) return mul_w8_1<DIR>(a);
+  else if constexpr (M == 3) return cmul(a, make_float2(HG_SIN_PI_8, s * HG_COS_PI_8));
+  else if constexpr (M == 4) return mul_dir_i<DIR>(a);
+  else if constexpr (M == 6) return mul_w8_3<DIR>(a);
+  else  // M == 9: angle 9 pi / 8
+    return cmul(a, make_float2(-HG_COS_PI_8, -s * HG_SIN_PI_8));
+}
+
+template <int DIR> __device__ __forceinline__ void dft16(float2* a) {
+  // n = n2 + 4 n1, k = k1 + 4 k2: inner 4-point DFTs over n1, twiddle w16^(n2 k1),
+  // outer 4-point DFTs over n2.
+  float2 b[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 x0 = a[n2], x1 = a[n2 + 4], x2 = a[n2 + 8], x3 = a[n2 + 12];
+    dft4<DIR>(x0, x1, x2, x3);
+    b[n2 * 4 + 0] = x0; b[n2 * 4 + 1] = x1; b[n2 * 4 + 2] = x2; b[n2 * 4 + 3] = x3;
+  }
+  b[1 * 4 + 1] = mul_w16<DIR, 1>(b[1 * 4 + 1]);
+  b[1 * 4 + 2] = mul_w16<DIR, 2>(b[1 * 4 + 2]);
+  b[1 * 4 + 3] = mul_w16<DIR, 3>(b[1 * 4 + 3]);
+  b[2 * 4 + 1] = mul_w16<DIR, 2>(b[2 * 4 + 1]);
+  b[2 * 4 + 2] = mul_w16<DIR, 4>(b[2 * 4 + 2]);
+  b[2 * 4 + 3] = mul_w16<DIR, 6>(b[2 * 4 + 3]);
+  b[3 * 4 + 1] = mul_w16<DIR, 3>(b[3 * 4 + 1]);
+  b[3 * 4 + 2] = mul_w16<DIR, 6>(b[3 * 4 + 2]);
+  b[3 * 4 + 3] = mul_w16<DIR, 9>(b[3 * 4 + 3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 y0 = b[k1], y1 = b[4 + k1], y2 = b[8 + k1], y3 = b[12 + k1];
+    dft4<DIR>(y0, y1, y2, y3);
+    a[k1] = y0; a[k1 + 4] = y1; a[k1 + 8] = y2; a[k1 + 12] = y3;
+  }
+}
+
+template <int DIR> __device__ __forceinline__ void dft3(float2* a) {
+  float2 t = cadd(a[1], a[2]);
+  float2 d = mul_dir_i<DIR>(cscale(csub(a[1], a[2]), HG_SIN_PI_3));
+  float2 m = make_float2(a[0].x - 0.5f * t.x, a[0].y - 0.5f * t.y);
+  a[0] = cadd(a[0], t);
+  a[1] = cadd(m, d);
+  a[2] = csub(m, d);
+}
+
+template <int DIR> __device__ __forceinline__ void dft5(float2* a) {
+  float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+  float2 d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+  float2 b1 = make_float2(a[0].x + HG_COS_2PI_5 * t1.x + HG_COS_4PI_5 * t2.x,
+                          a[0].y + HG_COS_2PI_5 * t1.y + HG_COS_4PI_5 * t2.y);
+  float2 b2 = make_float2(a[0].x + HG_COS_4PI_5 * t1.x + HG_COS_2PI_5 * t2.x,
+                          a[0].y + HG_COS_4PI_5 * t1.y + HG_COS_2PI_5 * t2.y);
+  float2 e1 = mul_dir_i<DIR>(make_float2(HG_SIN_2PI_5 * d1.x + HG_SIN_4PI_5 * d2.x,
+                                         HG_SIN_2PI_5 * d1.y + HG_SIN_4PI_5 * d2.y));
+  float2 e2 = mul_dir_i<DIR>(make_float2(HG_SIN_4PI_5 * d1.x - HG_SIN_2PI_5 * d2.x,
+                                         HG_SIN_4PI_5 * d1.y - HG_SIN_2PI_5 * d2.y));
+  a[0] = cadd(a[0], cadd(t1, t2));
+  a[1] = cadd(b1, e1);
+  a[4] = csub(b1, e1);
+  a[2] = cadd(b2, e2);
+  a[3] = csub(b2, e2);
+}
+
+template <int R, int DIR> __device__ __forceinline__ void dft(float2* a) {
+  static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 8 || R == 16, "unsupported radix");
+  if constexpr (R == 2) dft2<DIR>(a);
+  else if constexpr (R == 3) dft3<DIR>(a);
+  else if constexpr (R == 4) dft4<DIR>(a);
+  else if constexpr (R == 5) dft5<DIR>(a);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else dft16<DIR>(a);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time transform plan
+// ---------------------------------------------------------------------------
+template <int N_, int T_, int... Rs>
+struct Plan {
+  static constexpr int N = N_;
+  static constexpr int T = T_;
+  static constexpr int S = sizeof...(Rs);
+  static constexpr int R[S] = {Rs...};
+
+  // radix of stage s when the stages run in forward (REV = false) or reversed order
+  static constexpr int radix(int s, bool rev) { return rev ? R[S - 1 - s] : R[s]; }
+  static constexpr int ns(int s, bool rev) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i, rev);
+    return p;
+  }
+  static constexpr int rounds(int s, bool rev) { return (N / radix(s, rev) + T - 1) / T; }
+  static constexpr bool full(int s, bool rev) { return (N / radix(s, rev)) % T == 0; }
+  static constexpr int regs_() {
+    int m = 0;
+    for (int s = 0; s < S; ++s) {
+      int a = radix(s, false) * rounds(s, false);
+      int b = radix(s, true) * rounds(s, true);
+      m = a > m ? a : m;
+      m = b > m ? b : m;
+    }
+    return m;
+  }
+  static constexpr int REGS = regs_();
+  static constexpr bool palindrome_() {
+    for (int s = 0; s < S; ++s)
+      if (R[s] != R[S - 1 - s]) return false;
+    return true;
+  }
+  // reversed order has the same stages, so both directions share twiddles
+  static constexpr bool PALINDROME = palindrome_();
+  static constexpr int product_() {
+    int p = 1;
+    for (int s = 0; s < S; ++s) p *= R[s];
+    return p;
+  }
+  static_assert(product_() == N, "radices must multiply to N");
+  static_assert(S >= 2, "at least two stages (one LDS exchange) per transform");
+  static_assert(T <= 1024, "team too large");
+};
+
+// LDS padding: one spare complex slot every 2^PAD_LOG slots keeps the strided
+// Stockham writes off a single bank.
+constexpr int PAD_LOG = 4;
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> PAD_LOG); }
+__host__ __device__ constexpr int lds_len(int n) { return lds_pad(n - 1) + 1; }
+
+// Addressing of one team's LDS region: element i lives at base[lds_pad(i) * MUL].
+template <int MUL>
+struct LdsView {
+  float2* base;
+  __device__ __forceinline__ float2& at(int i) const { return base[lds_pad(i) * MUL]; }
+};
+
+// Synchronisation between exchange phases.  A team inside one wavefront only
+// needs the wavefront's LDS operations ordered; a wider team needs s_barrier.
+template <bool WAVE_SYNC> __device__ __forceinline__ void team_sync() {
+  if constexpr (WAVE_SYNC) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Register layout of the first stage (LAST = false) or the output of the last
+// stage (LAST = true) of a run in the given order: slot m * R + r holds element
+// t + m T + r N / R.
+template <class P, bool REV, bool LAST> struct Layout {
+  static constexpr int s = LAST ? P::S - 1 : 0;
+  static constexpr int R = P::radix(s, REV);
+  static constexpr int ROUNDS = P::rounds(s, REV);
+  static constexpr bool FULL = P::full(s, REV);
+  static constexpr int STRIDE = P::N / R;
+  __device__ __forceinline__ static bool valid(int t, int m) { return FULL || (t + m * P::T < STRIDE); }
+  __device__ __forceinline__ static int index(int t, int m, int r) { return t + m * P::T + r * STRIDE; }
+};
+
+// Visit every (register slot, element index) pair of a layout.
+template <class L, class F>
+__device__ __forceinline__ void for_layout(int t, F&& f) {
+#pragma unroll
+  for (int m = 0; m < L::ROUNDS; ++m)
+#pragma unroll
+    for (int r = 0; r < L::R; ++r)
+      if (L::valid(t, m)) f(m * L::R + r, L::index(t, m, r));
+}
+
+// ---------------------------------------------------------------------------
+// per-thread twiddles: stage s needs w^(r k), r = 1..R-1, for the k of each
+// butterfly the thread owns; when T is a multiple of Ns all of a thread's
+// butterflies in that stage share k.
+// ---------------------------------------------------------------------------
+template <class P, bool REV>
+struct TwRegs {
+  static constexpr int sets(int s) {
+    return P::ns(s, REV) == 1 ? 0 : ((P::T % P::ns(s, REV) == 0) ? 1 : P::rounds(s, REV));
+  }
+  static constexpr int offset(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i) o += sets(i) * (P::radix(i, REV) - 1);
+    return o;
+  }
+  static constexpr int TOTAL = offset(P::S);
+  float2 w[TOTAL > 0 ? TOTAL : 1];
+
+  template <int S_>
+  __device__ __forceinline__ void load_stage(const float2* __restrict__ tw, int t) {
+    constexpr int R = P::radix(S_, REV);
+    constexpr int NS = P::ns(S_, REV);
+    constexpr int SETS = sets(S_);
+    constexpr int TWS = P::N / (NS * R);
+    constexpr int OFF = offset(S_);
+#pragma unroll
+    for (int set = 0; set < SETS; ++set) {
+      const int k = (t + set * P::T) % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[OFF + set * (R - 1) + r - 1] = tw[r * k * TWS];
+    }
+    if constexpr (S_ + 1 < P::S) load_stage<S_ + 1>(tw, t);
+  }
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) { load_stage<0>(tw, t); }
+};
+
+// One radix stage in registers: twiddle then R-point DFTs.
+template <class P, int S_, bool REV, int DIR, class TW>
+__device__ __forceinline__ void stage_compute(float2* v, int t, const TW& tw) {
+  constexpr int R = P::radix(S_, REV);
+  constexpr int NS = P::ns(S_, REV);
+  constexpr int NR = P::N / R;
+  constexpr int ROUNDS = P::rounds(S_, REV);
+  constexpr bool SHARED = (NS > 1) && (P::T % NS == 0);
+  constexpr int OFF = TW::offset(S_);
+#pragma unroll
+  for (int m = 0; m < ROUNDS; ++m) {
+    const int j = t + m * P::T;
+    if (P::full(S_, REV) || j < NR) {
+      if constexpr (NS > 1) {
+        const int set = SHARED ? 0 : m;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw.w[OFF + set * (R - 1) + r - 1];
+          v[m * R + r] = DIR < 0 ? cmul(v[m * R + r], w) : cmulconj(v[m * R + r], w);
+        }
+      }
+      dft<R, DIR>(&v[m * R]);
+    }
+  }
+}
+
+// Move stage S_ outputs to the inputs of stage S_+1 through LDS.
+template <class P, int S_, bool REV, bool WAVE_SYNC, int MUL>
+__device__ __forceinline__ void stage_exchange(float2* v, int t, LdsView<MUL> lds) {
+  constexpr int R = P::radix(S_, REV);
+  constexpr int NS = P::ns(S_, REV);
+  constexpr int NR = P::N / R;
+  constexpr int ROUNDS = P::rounds(S_, REV);
+  constexpr int R2 = P::radix(S_ + 1, REV);
+  constexpr int NR2 = P::N / R2;
+  constexpr int ROUNDS2 = P::rounds(S_ + 1, REV);
+#pragma unroll
+  for (int m = 0; m < ROUNDS; ++m) {
+    const int j = t + m * P::T;
+    if (P::full(S_, REV) || j < NR) {
+      const int k = j % NS;
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds.at(base + r * NS) = v[m * R + r];
+    }
+  }
+  team_sync<WAVE_SYNC>();
+#pragma unroll
+  for (int m = 0; m < ROUNDS2; ++m) {
+    const int j = t + m * P::T;
+    if (P::full(S_ + 1, REV) || j < NR2) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[m * R2 + r] = lds.at(j + r * NR2);
+    }
+  }
+  team_sync<WAVE_SYNC>();
+}
+
+template <class P, int S_, bool REV, int DIR, bool WAVE_SYNC, int MUL, class TW>
+__device__ __forceinline__ void run_from(float2* v, int t, LdsView<MUL> lds, const TW& tw) {
+  stage_compute<P, S_, REV, DIR>(v, t, tw);
+  if constexpr (S_ + 1 < P::S) {
+    stage_exchange<P, S_, REV, WAVE_SYNC, MUL>(v, t, lds);
+    run_from<P, S_ + 1, REV, DIR, WAVE_SYNC, MUL>(v, t, lds, tw);
+  }
+}
+
+// Full transform of the team's sequence.  On entry v holds the first-stage
+// layout of order REV, on exit the last-stage layout.  tw must have been
+// loaded for order REV (or for either order when the plan is a palindrome).
+template <class P, bool REV, int DIR, bool WAVE_SYNC, int MUL, class TW>
+__device__ __forceinline__ void fft_run(float2* v, int t, LdsView<MUL> lds, const TW& tw) {
+  run_from<P, 0, REV, DIR, WAVE_SYNC, MUL>(v, t, lds, tw);
+}
+
+// Twiddle registers for running order REV: the forward set when the plan is a
+// palindrome (both orders have identical stages).
+template <class P, bool REV>
+using TwFor = TwRegs<P, P::PALINDROME ? false : REV>;
+
+}  // namespace hg

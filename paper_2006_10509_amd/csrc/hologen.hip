@@ -1,0 +1,570 @@
+// Host runtime of libhologen: plan creation (FP64 tables rounded to FP32),
+// argument validation, workspace layout and the launch sequences of
+// hg_propagate, hg_gs_iterate and hg_ospr.
+//
+// The plan plays the part of the paper's AlgorithmCuda base object, which
+// keeps the problem's images and parameters and the handles to their device
+// copies (Sec. 7.3; Sec. 4, Algorithm Interface); here the large images stay
+// caller-owned device buffers and the plan keeps only small constant tables.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hologen.h"
+#include "reduce.hpp"
+
+using namespace hg;
+
+namespace {
+
+thread_local hg_status g_last_status = HG_OK;
+thread_local std::string g_last_detail;
+thread_local std::string g_error_text;
+
+hg_status fail(hg_status s, const std::string& detail) {
+  g_last_status = s;
+  g_last_detail = detail;
+  return s;
+}
+
+const char* status_text(hg_status s) {
+  switch (s) {
+    case HG_OK: return "success";
+    case HG_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case HG_ERR_UNSUPPORTED_SIZE: return "unsupported transform size";
+    case HG_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case HG_ERR_DEVICE: return "device error";
+    case HG_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// per-length kernel tables (each filled in by its own translation unit)
+// ---------------------------------------------------------------------------
+}  // namespace
+
+#define HG_DECL_ENTRY(N) namespace hg { const LengthEntry* length_entry_##N(); }
+HG_FOR_EACH_LENGTH(HG_DECL_ENTRY)
+
+namespace {
+
+#define HG_ENTRY_PTR(N) hg::length_entry_##N(),
+
+const LengthEntry* find_length(int n) {
+  static const LengthEntry* const table[] = {HG_FOR_EACH_LENGTH(HG_ENTRY_PTR)};
+  for (const LengthEntry* e : table)
+    if (e->n == n) return e;
+  return nullptr;
+}
+
+bool smooth_235(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+hipError_t prepare_kernels(const LengthEntry* e) {
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
+  chk(allow_lds(e->row.prop_fwd, e->row.lds));
+  chk(allow_lds(e->row.prop_inv, e->row.lds));
+  chk(allow_lds(e->row.gs_start, e->row.lds));
+  for (auto& mode : e->row.gs_row)
+    for (auto k : mode) chk(allow_lds(k, e->row.lds));
+  chk(allow_lds(e->row.ospr_a, e->row.lds));
+  chk(allow_lds(e->row.ospr_c, e->row.lds));
+  chk(allow_lds(e->col.prop_fwd, e->col.lds));
+  chk(allow_lds(e->col.prop_inv, e->col.lds));
+  chk(allow_lds(e->col.gs_col, e->col.lds));
+  chk(allow_lds(e->col.gs_col_nmse, e->col.lds));
+  chk(allow_lds(e->col.ospr_b, e->col.lds));
+  return err;
+}
+
+constexpr int kNmseChunk = 128;   // states reduced per k_nmse_reduce launch
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+std::vector<float2> to_f32(const std::vector<double>& re, const std::vector<double>& im) {
+  std::vector<float2> out(re.size());
+  for (size_t i = 0; i < re.size(); ++i) out[i] = make_float2((float)re[i], (float)im[i]);
+  return out;
+}
+
+// exp(-2 pi i m / n), m < n, evaluated in FP64 with the exponent reduced exactly.
+std::vector<float2> twiddles(int n) {
+  std::vector<double> re(n), im(n);
+  for (int m = 0; m < n; ++m) {
+    double a = -2.0 * M_PI * (double)m / (double)n;
+    re[m] = std::cos(a);
+    im[m] = std::sin(a);
+  }
+  return to_f32(re, im);
+}
+
+// 1D quadratic phase exp(i pi ((j - n/2) pitch)^2 / (lambda z)) times `scale`, optionally conjugated.
+std::vector<float2> chirp(int n, double pitch, double lambda_z, std::complex<double> scale, bool conj) {
+  std::vector<double> re(n), im(n);
+  for (int j = 0; j < n; ++j) {
+    double c = (double)(j - n / 2) * pitch;
+    double ph = M_PI * c * c / lambda_z;
+    std::complex<double> v = std::polar(1.0, conj ? -ph : ph) * scale;
+    re[j] = v.real();
+    im[j] = v.imag();
+  }
+  return to_f32(re, im);
+}
+
+}  // namespace
+
+struct hg_plan_s {
+  hg_plan_desc desc;
+  const LengthEntry* row;   // kernels for rows (length = width)
+  const LengthEntry* col;   // kernels for columns (length = height)
+  float2* tw_w = nullptr;   // twiddles of length width
+  float2* tw_h = nullptr;   // twiddles of length height (aliases tw_w if equal)
+  float2* q1y = nullptr;    // Fresnel source chirp
+  float2* q1x = nullptr;
+  // Fresnel propagation tables: forward pre = Q1, post = c Q2;
+  // inverse pre = conj(Q2)/c, post = conj(Q1)
+  float2* fwd_post_y = nullptr;
+  float2* fwd_post_x = nullptr;
+  float2* inv_pre_y = nullptr;
+  float2* inv_pre_x = nullptr;
+  float2* inv_post_y = nullptr;
+  float2* inv_post_x = nullptr;
+  float2* lvl_tab = nullptr;
+  int levels = 0;           // quantiser levels used by GS (0 = continuous)
+  int row_blocks = 0, col_blocks = 0;
+  size_t off_scalars = 0, off_stats = 0, off_partials = 0, ws_bytes = 0;
+  std::vector<void*> allocations;
+  // diagnostics: event pairs around launches of one kernel kind
+  int timed_kernel = 0;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_used = 0;
+  hipError_t ev_error = hipSuccess;
+};
+
+namespace {
+
+hg_status upload(hg_plan p, const std::vector<float2>& host, float2** dst) {
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, host.size() * sizeof(float2));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? HG_ERR_OUT_OF_MEMORY : HG_ERR_DEVICE,
+                std::string("hipMalloc of plan table: ") + hipGetErrorString(e));
+  }
+  p->allocations.push_back(d);
+  e = hipMemcpy(d, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(HG_ERR_DEVICE, std::string("hipMemcpy of plan table: ") + hipGetErrorString(e));
+  *dst = static_cast<float2*>(d);
+  return HG_OK;
+}
+
+void free_plan(hg_plan p) {
+  for (void* d : p->allocations) (void)hipFree(d);
+  for (hipEvent_t e : p->ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->ev_stop) (void)hipEventDestroy(e);
+  delete p;
+}
+
+// Launch helper: brackets the launch with timing events when `kind` is timed.
+template <class F>
+void launch(hg_plan p, int kind, hipStream_t s, F&& f) {
+  const bool timed = p->timed_kernel == kind && p->ev_error == hipSuccess;
+  if (timed) {
+    if (p->ev_used == p->ev_start.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      hipError_t e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&b);
+      if (e != hipSuccess) {
+        p->ev_error = e;
+        f();
+        return;
+      }
+      p->ev_start.push_back(a);
+      p->ev_stop.push_back(b);
+    }
+    hipError_t e = hipEventRecord(p->ev_start[p->ev_used], s);
+    if (e != hipSuccess) p->ev_error = e;
+  }
+  f();
+  if (timed && p->ev_error == hipSuccess) {
+    hipError_t e = hipEventRecord(p->ev_stop[p->ev_used], s);
+    if (e != hipSuccess) p->ev_error = e;
+    ++p->ev_used;
+  }
+}
+
+hg_status validate_desc(const hg_plan_desc* d) {
+  if (!d) return fail(HG_ERR_INVALID_ARGUMENT, "desc is NULL");
+  for (int n : {d->width, d->height}) {
+    if (n < 2 || n > 8192) return fail(HG_ERR_INVALID_ARGUMENT, "width/height must be in [2, 8192]");
+    if (!smooth_235(n)) return fail(HG_ERR_UNSUPPORTED_SIZE, "width/height must be of the form 2^a 3^b 5^c");
+    if (!find_length(n))
+      return fail(HG_ERR_UNSUPPORTED_SIZE, "no transform of length " + std::to_string(n) + " in this build");
+  }
+  if (d->propagation != HG_FOURIER && d->propagation != HG_FRESNEL)
+    return fail(HG_ERR_INVALID_ARGUMENT, "propagation must be HG_FOURIER or HG_FRESNEL");
+  if (d->propagation == HG_FRESNEL) {
+    for (double v : {d->wavelength, d->pixel_pitch, d->distance})
+      if (!std::isfinite(v) || !(v > 0.0))
+        return fail(HG_ERR_INVALID_ARGUMENT, "Fresnel wavelength, pixel_pitch and distance must be finite and > 0");
+  }
+  switch (d->modulation) {
+    case HG_PHASE:
+      if (d->levels != 0) return fail(HG_ERR_INVALID_ARGUMENT, "levels must be 0 for HG_PHASE");
+      break;
+    case HG_PHASE_QUANTISED:
+      if (d->levels < 2 || d->levels > 256)
+        return fail(HG_ERR_INVALID_ARGUMENT, "levels must be in [2, 256] for HG_PHASE_QUANTISED");
+      break;
+    case HG_BINARY_PHASE:
+      if (d->levels != 2) return fail(HG_ERR_INVALID_ARGUMENT, "levels must be 2 for HG_BINARY_PHASE");
+      break;
+    default:
+      return fail(HG_ERR_INVALID_ARGUMENT, "modulation must be HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE");
+  }
+  return HG_OK;
+}
+
+hg_status launch_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return HG_OK;
+}
+
+struct Workspace {
+  float2* field;
+  Scalars* sc;
+  double* stats;
+  float* partials;
+};
+
+Workspace carve(hg_plan p, void* ws) {
+  char* b = static_cast<char*>(ws);
+  return {reinterpret_cast<float2*>(b), reinterpret_cast<Scalars*>(b + p->off_scalars),
+          reinterpret_cast<double*>(b + p->off_stats), reinterpret_cast<float*>(b + p->off_partials)};
+}
+
+size_t npix(hg_plan p) { return (size_t)p->desc.width * (size_t)p->desc.height; }
+
+int stats_blocks(size_t n) {
+  size_t b = (n + (size_t)STATS_THREADS * 16 - 1) / ((size_t)STATS_THREADS * 16);
+  if (b < 1) b = 1;
+  if (b > (size_t)STATS_MAX_BLOCKS) b = STATS_MAX_BLOCKS;
+  return (int)b;
+}
+
+void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const float* illum, double intensity_sum,
+                   hipStream_t s) {
+  const size_t n = npix(p);
+  const int nb = stats_blocks(n);
+  hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, w.stats, nb, n, illum ? 1 : 0,
+                     intensity_sum, w.sc);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI (the only symbols the library exports)
+// ===========================================================================
+#pragma GCC visibility push(default)
+extern "C" {
+
+const char* hg_error(hg_status s) {
+  g_error_text = status_text(s);
+  if (s != HG_OK && s == g_last_status && !g_last_detail.empty()) g_error_text += ": " + g_last_detail;
+  return g_error_text.c_str();
+}
+
+int32_t hg_length_supported(int32_t n) { return find_length(n) ? 1 : 0; }
+
+hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
+  if (!out) return fail(HG_ERR_INVALID_ARGUMENT, "out is NULL");
+  hg_status st = validate_desc(desc);
+  if (st != HG_OK) return st;
+  hg_plan p = new hg_plan_s();
+  p->desc = *desc;
+  const int W = desc->width, H = desc->height;
+  p->row = find_length(W);
+  p->col = find_length(H);
+  hipError_t e = prepare_kernels(p->row);
+  if (e == hipSuccess) e = prepare_kernels(p->col);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return fail(HG_ERR_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  }
+  st = upload(p, twiddles(W), &p->tw_w);
+  if (st == HG_OK) {
+    if (H == W) p->tw_h = p->tw_w;
+    else st = upload(p, twiddles(H), &p->tw_h);
+  }
+  if (st == HG_OK && desc->propagation == HG_FRESNEL) {
+    const double lz = desc->wavelength * desc->distance;
+    const double pitch = desc->pixel_pitch;
+    const double py_out = lz / ((double)H * pitch), px_out = lz / ((double)W * pitch);
+    const double kz = 2.0 * M_PI * std::fmod(desc->distance / desc->wavelength, 1.0);
+    const std::complex<double> pref = std::polar(1.0, kz) / std::complex<double>(0.0, lz) * (pitch * pitch);
+    const std::complex<double> one(1.0, 0.0);
+    st = upload(p, chirp(H, pitch, lz, one, false), &p->q1y);
+    if (st == HG_OK) st = upload(p, chirp(W, pitch, lz, one, false), &p->q1x);
+    if (st == HG_OK) st = upload(p, chirp(H, py_out, lz, pref, false), &p->fwd_post_y);
+    if (st == HG_OK) st = upload(p, chirp(W, px_out, lz, one, false), &p->fwd_post_x);
+    if (st == HG_OK) st = upload(p, chirp(H, py_out, lz, one / pref, true), &p->inv_pre_y);
+    if (st == HG_OK) st = upload(p, chirp(W, px_out, lz, one, true), &p->inv_pre_x);
+    if (st == HG_OK) st = upload(p, chirp(H, pitch, lz, one, true), &p->inv_post_y);
+    if (st == HG_OK) st = upload(p, chirp(W, pitch, lz, one, true), &p->inv_post_x);
+  }
+  if (desc->modulation == HG_PHASE_QUANTISED || desc->modulation == HG_BINARY_PHASE) {
+    p->levels = desc->levels;
+    if (st == HG_OK) {
+      std::vector<double> re(p->levels), im(p->levels);
+      for (int l = 0; l < p->levels; ++l) {
+        re[l] = std::cos(2.0 * M_PI * l / p->levels);
+        im[l] = std::sin(2.0 * M_PI * l / p->levels);
+      }
+      st = upload(p, to_f32(re, im), &p->lvl_tab);
+    }
+  }
+  if (st != HG_OK) {
+    free_plan(p);
+    return st;
+  }
+  p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
+  p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
+  const size_t n = (size_t)W * H;
+  p->off_scalars = align_up(n * sizeof(float2));
+  p->off_stats = p->off_scalars + align_up(sizeof(Scalars));
+  p->off_partials = p->off_stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
+  const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
+  p->ws_bytes = p->off_partials + align_up((size_t)kNmseChunk * nwg * sizeof(float));
+  *out = p;
+  return HG_OK;
+}
+
+hg_status hg_plan_destroy(hg_plan plan) {
+  if (plan) free_plan(plan);
+  return HG_OK;
+}
+
+size_t hg_workspace_bytes(hg_plan plan) { return plan ? plan->ws_bytes : 0; }
+
+hg_status hg_propagate(hg_plan p, const void* in_c64, void* out_c64, int32_t direction, void* workspace,
+                       hipStream_t stream) {
+  (void)workspace;
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!in_c64 || !out_c64) return fail(HG_ERR_INVALID_ARGUMENT, "in/out is NULL");
+  if (direction != HG_FORWARD && direction != HG_INVERSE)
+    return fail(HG_ERR_INVALID_ARGUMENT, "direction must be HG_FORWARD or HG_INVERSE");
+  const int W = p->desc.width, H = p->desc.height;
+  const bool fres = p->desc.propagation == HG_FRESNEL;
+  const bool fwd = direction == HG_FORWARD;
+  PropRowArgs ra{};
+  ra.in = static_cast<const float2*>(in_c64);
+  ra.out = static_cast<float2*>(out_c64);
+  ra.H = H;
+  ra.tw = p->tw_w;
+  PropColArgs ca{};
+  ca.io = static_cast<float2*>(out_c64);
+  ca.W = W;
+  ca.tw = p->tw_h;
+  ca.scale = fwd ? 1.0f : (float)(1.0 / ((double)W * (double)H));
+  if (fres) {
+    ra.sx_in = ra.sx_out = W / 2;
+    ca.sy_in = ca.sy_out = H / 2;
+    if (fwd) {
+      ra.pre_y = p->q1y; ra.pre_x = p->q1x;
+      ca.post_y = p->fwd_post_y; ca.post_x = p->fwd_post_x;
+    } else {
+      ra.pre_y = p->inv_pre_y; ra.pre_x = p->inv_pre_x;
+      ca.post_y = p->inv_post_y; ca.post_x = p->inv_post_x;
+    }
+  }
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+  launch(p, HG_KERNEL_PROP_ROW, stream, [&] {
+    hipLaunchKernelGGL(fwd ? rk.prop_fwd : rk.prop_inv, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+  });
+  launch(p, HG_KERNEL_PROP_COL, stream, [&] {
+    hipLaunchKernelGGL(fwd ? ck.prop_fwd : ck.prop_inv, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+  });
+  return launch_status("hg_propagate launch");
+}
+
+hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumination, float* phase,
+                        uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (iterations < 0) return fail(HG_ERR_INVALID_ARGUMENT, "iterations must be >= 0");
+  const int W = p->desc.width, H = p->desc.height;
+  Workspace w = carve(p, workspace);
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+
+  GsRowArgs ra{};
+  ra.field = w.field;
+  ra.illum = illumination;
+  ra.H = H;
+  if (p->desc.propagation == HG_FRESNEL) {
+    ra.q1y = p->q1y;
+    ra.q1x = p->q1x;
+  }
+  ra.slm.lvl_tab = p->lvl_tab;
+  ra.slm.levels = p->levels;
+  ra.slm.inv_delta = p->levels ? (float)((double)p->levels / (2.0 * M_PI)) : 0.0f;
+  ra.slm.inv_delta_f64 = p->levels ? (double)p->levels / (2.0 * M_PI) : 0.0;
+  ra.slm.half_step = p->levels ? make_float2((float)std::cos(M_PI / p->levels), (float)std::sin(M_PI / p->levels))
+                               : make_float2(1.0f, 0.0f);
+  ra.tw = p->tw_w;
+
+  GsColArgs ca{};
+  ca.field = w.field;
+  ca.W = W;
+  ca.H = H;
+  ca.target = target_amp;
+  ca.sc = w.sc;
+  ca.tw = p->tw_h;
+
+  const int mode = p->levels == 0 ? GS_CONT
+                 : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
+  void (*gs_row)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
+
+  if (nmse) enqueue_stats(p, w, target_amp, illumination, 0.0, stream);
+
+  ra.phase0 = phase;
+  ra.phase_out = iterations == 0 ? phase : nullptr;
+  ra.levels_out = iterations == 0 ? levels : nullptr;
+  hipLaunchKernelGGL(rk.gs_start, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+
+  int chunk0 = 0;  // first state of the pending reduction chunk
+  for (int k = 0; k <= iterations; ++k) {
+    const bool last = k == iterations;
+    if (last && !nmse) break;
+    ca.partials = nmse ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
+    if (last) {
+      hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+    } else {
+      launch(p, HG_KERNEL_GS_REPLAY, stream, [&] {
+        hipLaunchKernelGGL(ck.gs_col, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+      });
+    }
+    if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
+      hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream, w.partials,
+                         p->col_blocks, (const Scalars*)w.sc, nmse + chunk0);
+      chunk0 = k + 1;
+    }
+    if (last) break;
+    ra.phase_out = k == iterations - 1 ? phase : nullptr;
+    ra.levels_out = k == iterations - 1 ? levels : nullptr;
+    launch(p, HG_KERNEL_GS_SLM, stream, [&] {
+      hipLaunchKernelGGL(gs_row, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+    });
+  }
+  return launch_status("hg_gs_iterate launch");
+}
+
+hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, int32_t n_sub, uint8_t* holograms,
+                  float* intensity, float* nmse, void* workspace, hipStream_t stream) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (p->desc.propagation != HG_FOURIER) return fail(HG_ERR_INVALID_ARGUMENT, "hg_ospr needs a HG_FOURIER plan");
+  if (!target_amp || !sub_phase || !intensity)
+    return fail(HG_ERR_INVALID_ARGUMENT, "target_amp, sub_phase and intensity are required");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (n_sub < 1) return fail(HG_ERR_INVALID_ARGUMENT, "n_sub must be >= 1");
+  const int W = p->desc.width, H = p->desc.height;
+  const size_t n = npix(p);
+  Workspace w = carve(p, workspace);
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+  if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, stream);
+
+  OsprRowArgs ra{};
+  ra.field = w.field;
+  ra.H = H;
+  ra.target = target_amp;
+  ra.intensity = intensity;
+  ra.inv_nsub = (float)(1.0 / (double)n_sub);
+  ra.sc = w.sc;
+  ra.tw = p->tw_w;
+  OsprColArgs ca{};
+  ca.field = w.field;
+  ca.W = W;
+  ca.tw = p->tw_h;
+  for (int s = 0; s < n_sub; ++s) {
+    ra.theta = sub_phase + (size_t)s * n;
+    ra.first = s == 0;
+    ra.last = s == n_sub - 1;
+    ra.partials = (ra.last && nmse) ? w.partials : nullptr;
+    ca.levels = holograms ? holograms + (size_t)s * n : nullptr;
+    launch(p, HG_KERNEL_OSPR_A, stream, [&] {
+      hipLaunchKernelGGL(rk.ospr_a, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+    });
+    launch(p, HG_KERNEL_OSPR_B, stream, [&] {
+      hipLaunchKernelGGL(ck.ospr_b, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+    });
+    launch(p, HG_KERNEL_OSPR_C, stream, [&] {
+      hipLaunchKernelGGL(rk.ospr_c, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+    });
+  }
+  if (nmse)
+    hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, w.partials, p->row_blocks,
+                       (const Scalars*)w.sc, nmse);
+  return launch_status("hg_ospr launch");
+}
+
+hg_status hg_timing_begin(hg_plan p, int32_t kernel) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (kernel < HG_KERNEL_GS_REPLAY || kernel > HG_KERNEL_PROP_COL)
+    return fail(HG_ERR_INVALID_ARGUMENT, "unknown kernel id");
+  p->timed_kernel = kernel;
+  p->ev_used = 0;
+  p->ev_error = hipSuccess;
+  return HG_OK;
+}
+
+hg_status hg_timing_end(hg_plan p, double* total_ms, int64_t* launches) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!total_ms || !launches) return fail(HG_ERR_INVALID_ARGUMENT, "total_ms/launches is NULL");
+  const size_t used = p->ev_used;
+  const hipError_t pending = p->ev_error;
+  p->timed_kernel = 0;
+  p->ev_used = 0;
+  p->ev_error = hipSuccess;
+  if (pending != hipSuccess) return fail(HG_ERR_DEVICE, std::string("timing events: ") + hipGetErrorString(pending));
+  double sum = 0.0;
+  if (used) {
+    hipError_t e = hipEventSynchronize(p->ev_stop[used - 1]);
+    if (e != hipSuccess) return fail(HG_ERR_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]);
+      if (e != hipSuccess) return fail(HG_ERR_DEVICE, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+      sum += ms;
+    }
+  }
+  *total_ms = sum;
+  *launches = (int64_t)used;
+  return HG_OK;
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

@@ -1,0 +1,675 @@
+// Pass kernels of the iterative Fourier-transform hologram loop.
+//
+// Every kernel is one HBM pass over the [H][W] complex64 field: a row pass
+// (1D FFT of each row, the contiguous axis) or a column pass (1D FFT of each
+// column through padded LDS tiles), with the pointwise steps of the method
+// fused into the load and store sides so that no separate elementwise pass
+// exists:
+//
+//   Gerchberg-Saxton (Sec. 7.3, HoloGenAlgGSCuda; Gerchberg & Saxton 1972):
+//     k_gs_row_start  phi0 -> SLM constraint -> * Q1 -> row FFT
+//     k_gs_col        column FFT -> NMSE partial, amplitude replacement
+//                     -> inverse column FFT          (replay plane)
+//     k_gs_row        inverse row FFT -> * conj(Q1) -> SLM constraint
+//                     [-> phase / level output] -> * Q1 -> row FFT
+//   One-Step Phase-Retrieval (Sec. 7.3, HoloGenAlgOSPRCuda; Cable et al. 2004):
+//     k_ospr_a        T e^{i theta} (ifftshift on load) -> inverse row FFT
+//     k_ospr_b        inverse column FFT -> binarise Re -> levels -> column FFT
+//     k_ospr_c        row FFT -> |.|^2 accumulated (fftshift on store) [-> NMSE]
+//   Propagation (Fourier / single-FFT Fresnel):
+//     k_prop_row, k_prop_col
+//
+// Conventions.  The field is row-major [H][W] complex64 (float2).  The forward
+// transform uses exp(-2 pi i ...) and is unnormalised; inverse transforms
+// inside the loops are left unscaled because every constraint that follows
+// them (phase-only projection, quantiser, sign test) is invariant to a
+// positive scale.  Q1 = q_y[y] q_x[x] is the Fresnel source chirp (tables of
+// H + W entries); a null q_y selects a Fourier hologram.
+//
+// Launch shape.  A row team is one wavefront when T = 64, so its row index is
+// wave-uniform and lives in a scalar register; teams past the last row load a
+// valid row and skip their stores, so no per-element branch exists.  Column
+// workgroups are mapped so that each XCD gets a contiguous range of column
+// tiles: the C * 8-byte row segments of neighbouring tiles share 128-byte
+// lines, and keeping them on one XCD lets that XCD's L2 serve them.
+#pragma once
+
+#include "fft_core.hpp"
+#include "sizes.hpp"
+
+#include <type_traits>
+
+namespace hg {
+
+constexpr float TWO_PI_F = 6.28318530717958647692f;
+
+// Device-side scalars computed once per call (see k_stats_final).
+struct Scalars {
+  float a;          // N_px / sum(I): intensity normaliser of the replay field
+  float b;          // N_px / sum(T^2): normaliser of the target intensity
+  double denom;     // N_px^2 sum(T^4) / sum(T^2)^2 = N_px^2 sum (T_I / sum T_I)^2
+  double sum_t2, sum_t4, sum_a2;
+};
+
+// SLM constraint shared by the GS kernels.
+struct SlmConstraint {
+  const float2* __restrict__ lvl_tab;  // exp(i 2 pi l / L), FP64-built; null = continuous
+  int levels;
+  float inv_delta;                     // L / (2 pi)
+  double inv_delta_f64;                // L / (2 pi) for the one-off quantisation of phi0
+  float2 half_step;                    // exp(i pi / L): rotates decision boundaries onto axes
+};
+
+// ---------------------------------------------------------------------------
+// SLM-plane constraint
+// ---------------------------------------------------------------------------
+// floor(angle / (pi/4)) of a non-zero vector, angle taken in [0, 2 pi),
+// without branches: fold the lower half-plane onto the upper one (angle - pi),
+// then the second quadrant onto the first (angle - pi/2), then compare the two
+// coordinates (angle >= pi/4).  Each boundary goes to the higher sector, as
+// floor() does: the upper half is y > 0 or (y == 0 and x > 0), the first
+// quadrant of it x > 0, and the upper octant v >= u.
+__device__ __forceinline__ int octant(float x, float y) {
+  const bool upper = (y > 0.0f) | ((y == 0.0f) & (x > 0.0f));
+  const float x1 = upper ? x : -x, y1 = upper ? y : -y;
+  const bool second = !(x1 > 0.0f);
+  const float u = second ? y1 : x1, v = second ? -x1 : y1;
+  return (upper ? 0 : 4) + (second ? 2 : 0) + (v >= u ? 1 : 0);
+}
+
+// Level of a complex value: floor(mod(atan2(Im, Re), 2 pi) / Delta + 1/2) mod L.
+// For L in {2, 4, 8} the value is first rotated by Delta/2, which puts the
+// decision boundaries on the axes and diagonals, and the level is read from
+// signs and magnitude comparisons; other L use atan2.  G = 0 has level 0.
+__device__ __forceinline__ int quant_level(float2 g, const SlmConstraint& slm) {
+  if (slm.levels == 8 || slm.levels == 4 || slm.levels == 2) {
+    if (g.x == 0.0f && g.y == 0.0f) return 0;
+    const float2 r = cmul(g, slm.half_step);
+    const int o = octant(r.x, r.y);
+    return slm.levels == 8 ? o : (slm.levels == 4 ? (o >> 1) : (o >> 2));
+  }
+  float th = atan2f(g.y, g.x);
+  if (th < 0.0f) th += TWO_PI_F;
+  int l = (int)floorf(th * slm.inv_delta + 0.5f);
+  return l >= slm.levels ? l - slm.levels : l;
+}
+
+// Level of a phase value in radians (any finite value), decided in FP64: the
+// starting phase is an input, so its quantisation is made exactly as the
+// definition states rather than in the precision of the loop.
+__device__ __forceinline__ int quant_phase(float phi, int levels, double inv_delta) {
+  long long l = (long long)floor((double)phi * inv_delta + 0.5) % levels;
+  return (int)(l < 0 ? l + levels : l);
+}
+
+// Unit-modulus value G/|G| (G = 0 -> 1).
+__device__ __forceinline__ float2 unit_of(float2 g) {
+  const float n2 = cnorm(g);
+  if (n2 > 0.0f) {
+    const float s = rsqrtf(n2);
+    return make_float2(g.x * s, g.y * s);
+  }
+  return make_float2(1.0f, 0.0f);
+}
+
+__device__ __forceinline__ float wrap_phase(float2 u) {
+  float p = atan2f(u.y, u.x);
+  if (p < 0.0f) p += TWO_PI_F;
+  if (p >= TWO_PI_F) p -= TWO_PI_F;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// addressing helpers
+// ---------------------------------------------------------------------------
+// Global loads and stores with a 32-bit unsigned byte offset from a base
+// pointer: the base stays in scalar registers and the address needs no 64-bit
+// arithmetic.  Every buffer the kernels touch is below 4 GiB.
+template <class T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stg(T* base, uint32_t i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
+// (i + s) mod n for 0 <= i, s < n
+template <int NC>
+__device__ __forceinline__ int wrap_add(int i, int s) {
+  if constexpr ((NC & (NC - 1)) == 0) return (i + s) & (NC - 1);
+  else { const int j = i + s; return j >= NC ? j - NC : j; }
+}
+__device__ __forceinline__ int wrap_add_rt(int i, int s, int n) {
+  const int j = i + s;
+  return j >= n ? j - n : j;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape helpers
+// ---------------------------------------------------------------------------
+// Workgroup b of n runs on XCD b % 8; give XCD x the contiguous tile range
+// [x * n/8, ...) so that neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, rem = n & 7;
+  const int x = b & 7, local = b >> 3;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
+}
+
+template <class C>
+struct RowTeam {
+  int t, team, y;
+  bool live;
+  __device__ __forceinline__ RowTeam(int H) {
+    using P = typename C::P;
+    team = threadIdx.x / P::T;
+    t = threadIdx.x % P::T;
+    int row = blockIdx.x * C::TEAMS + team;
+    if constexpr (P::T == 64) row = __builtin_amdgcn_readfirstlane(row);
+    live = row < H;
+    y = live ? row : H - 1;
+  }
+};
+
+// Wavefront then workgroup sum of one float per thread, fixed order.
+template <int THREADS>
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  static_assert(THREADS % 64 == 0, "whole wavefronts");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  constexpr int NW = THREADS / 64;
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NW; ++i) s += red[i];
+    }
+    return s;
+  }
+}
+
+extern __shared__ float2 hg_dyn_lds[];
+
+// ===========================================================================
+// Propagation passes: out = post * Sh_out(FFT2(Sh_in(pre * in))), separable
+// pre/post tables and cyclic shifts (Fourier: none; Fresnel: chirps + centring).
+// ===========================================================================
+struct PropRowArgs {
+  const float2* in;
+  float2* out;
+  int H;
+  int sx_in, sx_out;
+  const float2* pre_y;  // null -> no pre-multiply
+  const float2* pre_x;
+  const float2* tw;
+};
+
+template <int N, int DIR>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.in, row + wrap_add<N>(x, a.sx_in)); });
+  TwFor<P, false> tw;
+  tw.load(a.tw, t);
+  if (a.pre_y) {
+    const float2 py = a.pre_y[rt.y];
+    for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, ldg(a.pre_x, wrap_add<N>(x, a.sx_in)))); });
+  }
+  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, tw);
+  if (rt.live) for_layout<L1>(t, [&](int s, int k) { stg(a.out, row + wrap_add<N>(k, a.sx_out), v[s]); });
+}
+
+struct PropColArgs {
+  float2* io;
+  int W;
+  int sy_in, sy_out;
+  const float2* post_y;  // null -> no post-multiply
+  const float2* post_x;
+  float scale;
+  const float2* tw;
+};
+
+template <int N, int DIR>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_prop_col(PropColArgs a) {
+  using C = ColCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * C::C + c;
+  const bool live = col < a.W;
+  const uint32_t x = live ? col : a.W - 1;
+  LdsView<C::C> lds{hg_dyn_lds + c};
+  float2 v[P::REGS];
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)wrap_add<N>(y, a.sy_in) * a.W + x); });
+  TwFor<P, false> tw;
+  tw.load(a.tw, t);
+  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, tw);
+  if (live) {
+    const float2 px = a.post_y ? ldg(a.post_x, x) : make_float2(1.f, 0.f);
+    for_layout<L1>(t, [&](int s, int k) {
+      k = wrap_add<N>(k, a.sy_out);
+      float2 z = v[s];
+      if (a.post_y) z = cmul(z, cmul(ldg(a.post_y, k), px));
+      stg(a.io, (uint32_t)k * a.W + x, cscale(z, a.scale));
+    });
+  }
+}
+
+// ===========================================================================
+// Gerchberg-Saxton
+// ===========================================================================
+struct GsRowArgs {
+  float2* field;
+  const float* phase0;      // start kernel only: starting phase [H][W]
+  const float* illum;       // SLM amplitude A [H][W]; null -> 1
+  int H;
+  const float2* q1y;        // Fresnel source chirp; null -> Fourier
+  const float2* q1x;
+  SlmConstraint slm;
+  float* phase_out;         // non-null on the pass that produces the output state
+  uint8_t* levels_out;
+  const float2* tw;
+};
+
+// SLM-constraint variants of the steady-state row pass.
+enum { GS_CONT = 0, GS_QATAN = 1, GS_Q2 = 2, GS_Q4 = 4, GS_Q8 = 8 };
+__host__ __device__ constexpr int gs_mode_index(int mode) {
+  return mode == GS_CONT ? 0 : mode == GS_QATAN ? 1 : mode == GS_Q2 ? 2 : mode == GS_Q4 ? 3 : 4;
+}
+
+__device__ __forceinline__ void write_state(const GsRowArgs& a, uint32_t idx, float2 u, int level) {
+  if (a.slm.lvl_tab) {
+    if (a.phase_out) stg(a.phase_out, idx, (float)level * (TWO_PI_F / (float)a.slm.levels));
+    if (a.levels_out) stg(a.levels_out, idx, (uint8_t)level);
+  } else {
+    if (a.phase_out) stg(a.phase_out, idx, wrap_phase(u));
+    if (a.levels_out) stg(a.levels_out, idx, (uint8_t)0);
+  }
+}
+
+// phi0 -> H_0 = A exp(i C(phi0)) -> Q1 H_0 -> row FFT.  Runs once per call.
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  float ph[P::REGS];
+  for_layout<L0>(t, [&](int s, int x) { ph[s] = ldg(a.phase0, row + x); });
+  TwFor<P, false> tw;
+  tw.load(a.tw, t);
+  const float2 qy = a.q1y ? a.q1y[rt.y] : make_float2(1.f, 0.f);
+  const bool out = rt.live && (a.phase_out || a.levels_out);
+  for_layout<L0>(t, [&](int s, int x) {
+    float2 u;
+    int level = 0;
+    if (a.slm.lvl_tab) {
+      level = quant_phase(ph[s], a.slm.levels, a.slm.inv_delta_f64);
+      u = a.slm.lvl_tab[level];
+    } else {
+      float sn, cs;
+      sincosf(ph[s], &sn, &cs);
+      u = make_float2(cs, sn);
+    }
+    if (out) write_state(a, row + x, u, level);
+    float2 h = a.illum ? cscale(u, ldg(a.illum, row + x)) : u;
+    if (a.q1y) h = cmul(h, cmul(qy, ldg(a.q1x, x)));
+    v[s] = h;
+  });
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, tw);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+}
+
+// exp(i o pi / 4) for an octant index o in [0, 8), from the index bits: the
+// odd octants start from (1 + i)/sqrt(2), bit 1 turns by pi/2, bit 2 by pi.
+__device__ __forceinline__ float2 octant_value(int o) {
+  const bool odd = o & 1, quarter = o & 2, half = o & 4;
+  const float bx = odd ? HG_SQRT1_2 : 1.0f, by = odd ? HG_SQRT1_2 : 0.0f;
+  const float x = quarter ? -by : bx, y = quarter ? bx : by;
+  return half ? make_float2(-x, -y) : make_float2(x, y);
+}
+
+template <int MODE>
+__device__ __forceinline__ float2 slm_constrain(float2 g, const SlmConstraint& slm, int& level) {
+  if constexpr (MODE == GS_CONT) {
+    level = 0;
+    return unit_of(g);
+  } else if constexpr (MODE == GS_QATAN) {
+    level = quant_level(g, slm);
+    return slm.lvl_tab[level];
+  } else {
+    // L in {2, 4, 8}: octant of G exp(i pi / L); octant o <-> level o / (8 / L)
+    const float2 r = cmul(g, slm.half_step);
+    const int o = octant(r.x, r.y);
+    constexpr int SHIFT = MODE == GS_Q8 ? 0 : (MODE == GS_Q4 ? 1 : 2);
+    const bool zero = (g.x == 0.0f) & (g.y == 0.0f);
+    level = zero ? 0 : (o >> SHIFT);
+    return octant_value(level << SHIFT);
+  }
+}
+
+// Steady-state row pass: inverse row FFT -> conj(Q1) -> constraint -> Q1 -> row FFT.
+// The inverse runs the radices in reversed order so that its last-stage
+// register layout is the first-stage layout of the forward transform.
+template <int N, int MODE, bool FRES>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
+  using LF = Layout<P, false, false>;  // == last stage of the reversed run
+  using L1 = Layout<P, false, true>;
+  static_assert(LF::R == Layout<P, true, true>::R, "layout mismatch");
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  TwFor<P, false> twf;
+  twf.load(a.tw, t);
+  TwFor<P, true> twi;
+  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
+  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
+    if constexpr (P::PALINDROME) return twf; else return twi;
+  }();
+  float2 q[FRES ? P::REGS : 1];
+  if constexpr (FRES) {
+    const float2 qy = a.q1y[rt.y];
+    for_layout<LF>(t, [&](int s, int x) { q[s] = cmul(qy, ldg(a.q1x, x)); });
+  }
+  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
+  auto constrain_all = [&](auto out_tag, auto illum_tag) {
+    constexpr bool OUT = decltype(out_tag)::value;
+    constexpr bool ILLUM = decltype(illum_tag)::value;
+    for_layout<LF>(t, [&](int s, int x) {
+      float2 g = v[s];
+      if constexpr (FRES) g = cmulconj(g, q[s]);
+      int level;
+      float2 u = slm_constrain<MODE>(g, a.slm, level);
+      if constexpr (OUT) write_state(a, row + x, u, level);
+      if constexpr (ILLUM) u = cscale(u, ldg(a.illum, row + x));
+      if constexpr (FRES) u = cmul(u, q[s]);
+      v[s] = u;
+    });
+  };
+  const bool out = rt.live && (a.phase_out || a.levels_out);
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (out) {
+    if (a.illum) constrain_all(T_{}, T_{}); else constrain_all(T_{}, F_{});
+  } else {
+    if (a.illum) constrain_all(F_{}, T_{}); else constrain_all(F_{}, F_{});
+  }
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+}
+
+struct GsColArgs {
+  float2* field;
+  int W;
+  int H;
+  const float* target;        // centred target amplitude [H][W]
+  const Scalars* sc;
+  float* partials;            // one float per workgroup for this state; null -> no NMSE
+  const float2* tw;
+};
+
+// Replay-plane pass: column FFT -> R_k; NMSE partial of |R_k|^2 against T^2;
+// REPLACE: R' = T R / |R| -> inverse column FFT -> field.
+template <int N, bool REPLACE>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
+  using C = ColCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  using LB = Layout<P, true, true>;
+  static_assert(LB::R == L0::R, "layout mismatch");
+  __shared__ float red[C::THREADS / 64];
+  const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int col = tile * C::C + c;
+  const bool live = col < a.W;
+  const uint32_t x = live ? col : a.W - 1;
+  LdsView<C::C> lds{hg_dyn_lds + c};
+  float2 v[P::REGS];
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
+  // target amplitude in FFT order: T_f[ky][x] = T[(ky + H/2) % H][(x + W/2) % W]
+  const uint32_t xs = wrap_add_rt(x, a.W / 2, a.W);
+  float tgt[P::REGS];
+  for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, (uint32_t)wrap_add<N>(ky, N / 2) * a.W + xs); });
+  TwFor<P, false> twf;
+  twf.load(a.tw, t);
+  TwFor<P, true> twi;
+  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
+  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
+    if constexpr (P::PALINDROME) return twf; else return twi;
+  }();
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  float acc = 0.f;
+  const bool nm = a.partials != nullptr;
+  const float sa = nm ? a.sc->a : 0.f;
+  const float sb = nm ? a.sc->b : 0.f;
+  for_layout<L1>(t, [&](int s, int) {
+    const float2 R = v[s];
+    const float tv = tgt[s];
+    const float I = cnorm(R);
+    const float d = I * sa - tv * tv * sb;
+    acc = fmaf(d, d, acc);
+    if constexpr (REPLACE) {
+      const float k = tv * rsqrtf(I);
+      v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(tv, 0.0f);
+    }
+  });
+  if (nm) {
+    const float s = block_sum<C::THREADS>(live ? acc : 0.0f, red);
+    if (threadIdx.x == 0) a.partials[tile] = s;
+  }
+  if constexpr (REPLACE) {
+    fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
+    if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
+  }
+}
+
+// ===========================================================================
+// OSPR
+// ===========================================================================
+struct OsprRowArgs {
+  float2* field;
+  int H;
+  const float* target;     // centred amplitude [H][W]
+  const float* theta;      // centred subframe phase [H][W] (pass A)
+  float* intensity;        // centred accumulator / output [H][W] (pass C)
+  int first, last;
+  float inv_nsub;
+  const Scalars* sc;
+  float* partials;         // pass C of the last subframe: NMSE partials
+  const float2* tw;
+};
+
+// Pass A: E = T exp(i theta) read through ifftshift -> inverse row FFT.
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t srow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
+  float th[P::REGS], am[P::REGS];
+  for_layout<L0>(t, [&](int s, int x) {
+    const uint32_t i = srow + wrap_add<N>(x, N / 2);
+    th[s] = ldg(a.theta, i);
+    am[s] = ldg(a.target, i);
+  });
+  TwFor<P, false> tw;
+  tw.load(a.tw, t);
+  for_layout<L0>(t, [&](int s, int) {
+    float sn, cs;
+    sincosf(th[s], &sn, &cs);
+    v[s] = make_float2(am[s] * cs, am[s] * sn);
+  });
+  fft_run<P, false, +1, C::WAVE_SYNC>(v, t, lds, tw);
+  const uint32_t row = (uint32_t)rt.y * N;
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+}
+
+struct OsprColArgs {
+  float2* field;
+  int W;
+  uint8_t* levels;   // [H][W] of this subframe, natural SLM order; may be null
+  const float2* tw;
+};
+
+// Pass B: inverse column FFT -> h = sign(Re G) -> level -> forward column FFT of h.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
+  using C = ColCfg<N>;
+  using P = typename C::P;
+  using LI = Layout<P, true, false>;
+  using LF = Layout<P, false, false>;
+  using L2 = Layout<P, false, true>;
+  const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * C::C + c;
+  const bool live = col < a.W;
+  const uint32_t x = live ? col : a.W - 1;
+  LdsView<C::C> lds{hg_dyn_lds + c};
+  float2 v[P::REGS];
+  for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
+  TwFor<P, false> twf;
+  twf.load(a.tw, t);
+  TwFor<P, true> twi;
+  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
+  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
+    if constexpr (P::PALINDROME) return twf; else return twi;
+  }();
+  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
+  const bool wl = live && a.levels;
+  for_layout<LF>(t, [&](int s, int y) {
+    const bool neg = !(v[s].x >= 0.0f);
+    if (wl) stg(a.levels, (uint32_t)y * a.W + x, (uint8_t)(neg ? 1 : 0));
+    v[s] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
+  });
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
+}
+
+// Pass C: row FFT -> |.|^2 -> accumulate into the centred intensity (fftshift on
+// store); the last subframe scales by 1/N_sub and adds the NMSE partials.
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  __shared__ float red[C::THREADS / 64];
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  const uint32_t orow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
+  const bool nm = a.last && a.partials;
+  float prev[P::REGS], tg[P::REGS];
+  for_layout<L1>(t, [&](int s, int k) {
+    const uint32_t i = orow + wrap_add<N>(k, N / 2);
+    prev[s] = a.first ? 0.0f : ldg(a.intensity, i);
+    tg[s] = nm ? ldg(a.target, i) : 0.0f;
+  });
+  TwFor<P, false> tw;
+  tw.load(a.tw, t);
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, tw);
+  float acc = 0.f;
+  const float sa = nm ? a.sc->a : 0.f;
+  const float sb = nm ? a.sc->b : 0.f;
+  for_layout<L1>(t, [&](int s, int k) {
+    float I = cnorm(v[s]) + prev[s];
+    if (a.last) {
+      I *= a.inv_nsub;
+      const float d = I * sa - tg[s] * tg[s] * sb;
+      acc = fmaf(d, d, acc);
+    }
+    if (rt.live) stg(a.intensity, orow + wrap_add<N>(k, N / 2), I);
+  });
+  if (a.partials) {
+    const float s = block_sum<C::THREADS>(rt.live ? acc : 0.0f, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-length kernel table (one translation unit per length fills it in)
+// ---------------------------------------------------------------------------
+struct RowKernels {
+  void (*prop_fwd)(PropRowArgs);
+  void (*prop_inv)(PropRowArgs);
+  void (*gs_start)(GsRowArgs);
+  void (*gs_row[5][2])(GsRowArgs);   // [gs_mode_index][Fresnel]
+  void (*ospr_a)(OsprRowArgs);
+  void (*ospr_c)(OsprRowArgs);
+  int teams, threads;
+  size_t lds;
+};
+struct ColKernels {
+  void (*prop_fwd)(PropColArgs);
+  void (*prop_inv)(PropColArgs);
+  void (*gs_col)(GsColArgs);
+  void (*gs_col_nmse)(GsColArgs);
+  void (*ospr_b)(OsprColArgs);
+  int cols, threads;
+  size_t lds;
+};
+struct LengthEntry {
+  int n;
+  RowKernels row;
+  ColKernels col;
+};
+
+template <int N>
+LengthEntry make_length_entry() {
+  LengthEntry e;
+  e.n = N;
+  e.row.prop_fwd = k_prop_row<N, -1>;
+  e.row.prop_inv = k_prop_row<N, +1>;
+  e.row.gs_start = k_gs_row_start<N>;
+  e.row.gs_row[0][0] = k_gs_row<N, GS_CONT, false>;
+  e.row.gs_row[0][1] = k_gs_row<N, GS_CONT, true>;
+  e.row.gs_row[1][0] = k_gs_row<N, GS_QATAN, false>;
+  e.row.gs_row[1][1] = k_gs_row<N, GS_QATAN, true>;
+  e.row.gs_row[2][0] = k_gs_row<N, GS_Q2, false>;
+  e.row.gs_row[2][1] = k_gs_row<N, GS_Q2, true>;
+  e.row.gs_row[3][0] = k_gs_row<N, GS_Q4, false>;
+  e.row.gs_row[3][1] = k_gs_row<N, GS_Q4, true>;
+  e.row.gs_row[4][0] = k_gs_row<N, GS_Q8, false>;
+  e.row.gs_row[4][1] = k_gs_row<N, GS_Q8, true>;
+  e.row.ospr_a = k_ospr_a<N>;
+  e.row.ospr_c = k_ospr_c<N>;
+  e.row.teams = RowCfg<N>::TEAMS;
+  e.row.threads = RowCfg<N>::THREADS;
+  e.row.lds = sizeof(float2) * RowCfg<N>::TEAMS * lds_len(N);
+  e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, true>, k_gs_col<N, false>, k_ospr_b<N>,
+           ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColCfg<N>::C * lds_len(N)};
+  return e;
+}
+
+}  // namespace hg

@@ -1,0 +1,100 @@
+// Per-call statistics and the deterministic NMSE reduction (host TU only).
+//
+// The paper's Normaliser provides vector normalisation (Sec. 7.3); here the
+// energy normalisation of the error metric needs sum T^2 and sum T^4 of the
+// target and sum A^2 of the illumination once per call, and the per-workgroup
+// partial sums of every state are combined in a fixed order so that the
+// reported NMSE is bitwise reproducible.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace hg {
+
+// ===========================================================================
+// Per-call statistics and the deterministic NMSE reduction
+// ===========================================================================
+constexpr int STATS_THREADS = 256;
+constexpr int STATS_MAX_BLOCKS = 512;
+
+template <int THREADS>
+__device__ __forceinline__ double block_sum_f64(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// sum T^2, sum T^4, sum A^2 per workgroup (FP64), fixed order.
+__global__ __launch_bounds__(STATS_THREADS) void k_stats_partial(const float* __restrict__ target,
+                                                                 const float* __restrict__ illum,
+                                                                 size_t n, double* __restrict__ part) {
+  __shared__ double red[STATS_THREADS];
+  double t2 = 0.0, t4 = 0.0, a2 = 0.0;
+  for (size_t i = (size_t)blockIdx.x * STATS_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * STATS_THREADS) {
+    const double tv = (double)target[i];
+    const double q = tv * tv;
+    t2 += q;
+    t4 += q * q;
+    if (illum) {
+      const double av = (double)illum[i];
+      a2 += av * av;
+    }
+  }
+  t2 = block_sum_f64<STATS_THREADS>(t2, red);
+  t4 = block_sum_f64<STATS_THREADS>(t4, red);
+  a2 = block_sum_f64<STATS_THREADS>(a2, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = t2;
+    part[blockIdx.x * 3 + 1] = t4;
+    part[blockIdx.x * 3 + 2] = a2;
+  }
+}
+
+// Combine the partials; sum I follows from Parseval: N_px sum A^2 for a GS
+// state (|H| = A), N_px^2 for an OSPR average of +-1 holograms (intensity_sum).
+__global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __restrict__ part, int nblk, size_t n,
+                                                               int has_illum, double intensity_sum,
+                                                               Scalars* __restrict__ sc) {
+  __shared__ double red[STATS_THREADS];
+  double t2 = 0.0, t4 = 0.0, a2 = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += STATS_THREADS) {
+    t2 += part[i * 3 + 0];
+    t4 += part[i * 3 + 1];
+    a2 += part[i * 3 + 2];
+  }
+  t2 = block_sum_f64<STATS_THREADS>(t2, red);
+  t4 = block_sum_f64<STATS_THREADS>(t4, red);
+  a2 = block_sum_f64<STATS_THREADS>(a2, red);
+  if (threadIdx.x == 0) {
+    const double npx = (double)n;
+    if (!has_illum) a2 = npx;
+    const double s_i = intensity_sum > 0.0 ? intensity_sum : npx * a2;
+    sc->sum_t2 = t2;
+    sc->sum_t4 = t4;
+    sc->sum_a2 = a2;
+    sc->a = (float)(npx / s_i);
+    sc->b = (float)(npx / t2);
+    sc->denom = npx * npx * t4 / (t2 * t2);
+  }
+}
+
+// nmse[k] = sum_wg partials[k][wg] / denom, one workgroup per state, fixed order.
+__global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce(const float* __restrict__ partials, int nwg,
+                                                               const Scalars* __restrict__ sc,
+                                                               float* __restrict__ nmse) {
+  __shared__ double red[STATS_THREADS];
+  const float* p = partials + (size_t)blockIdx.x * nwg;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];
+  s = block_sum_f64<STATS_THREADS>(s, red);
+  if (threadIdx.x == 0) nmse[blockIdx.x] = (float)(s / sc->denom);
+}
+
+}  // namespace hg

@@ -1,0 +1,72 @@
+// Transform lengths compiled into the library and the launch shape of each.
+//
+// A row pass gives every row (length W, the contiguous axis) to a team of T
+// threads and packs TEAMS rows into one workgroup.  A column pass gives every
+// column (length H) to a team and packs C adjacent columns into one
+// workgroup, so each global access covers C * 8 contiguous bytes per row.
+// Teams of at most 64 threads that do not straddle a wavefront exchange data
+// through LDS with wavefront-level ordering only; wider teams use s_barrier.
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace hg {
+
+template <int N> struct RowCfg;
+template <int N> struct ColCfg;
+
+#define HG_ROW_CFG(N_, TEAMS_, T_, ...)                                   \
+  template <> struct RowCfg<N_> {                                        \
+    using P = Plan<N_, T_, __VA_ARGS__>;                                 \
+    static constexpr int TEAMS = TEAMS_;                                 \
+    static constexpr int THREADS = TEAMS_ * T_;                          \
+    static constexpr bool WAVE_SYNC = (T_ <= 64) && (64 % T_ == 0);      \
+  };
+#define HG_COL_CFG(N_, C_, T_, ...)                                       \
+  template <> struct ColCfg<N_> {                                        \
+    using P = Plan<N_, T_, __VA_ARGS__>;                                 \
+    static constexpr int C = C_;                                         \
+    static constexpr int THREADS = C_ * T_;                              \
+    static constexpr bool WAVE_SYNC = (C_ * T_ <= 64);                   \
+  };
+
+//          N     rows/WG  T    radices
+HG_ROW_CFG(16,    64,     4,   4, 4)
+HG_ROW_CFG(32,    32,     8,   4, 2, 4)
+HG_ROW_CFG(64,    32,     8,   8, 8)
+HG_ROW_CFG(128,   16,    16,   8, 2, 8)
+HG_ROW_CFG(256,   16,    16,   16, 16)
+HG_ROW_CFG(512,    4,    64,   8, 8, 8)
+HG_ROW_CFG(1024,   4,    64,   16, 4, 16)
+HG_ROW_CFG(2048,   2,    64,   16, 8, 16)
+HG_ROW_CFG(4096,   2,   128,   16, 16, 16)
+HG_ROW_CFG(24,    32,     8,   8, 3)
+HG_ROW_CFG(60,    16,    16,   4, 3, 5)
+HG_ROW_CFG(90,    16,    16,   2, 3, 3, 5)
+HG_ROW_CFG(120,   16,    16,   8, 3, 5)
+HG_ROW_CFG(1080,   4,    64,   8, 3, 3, 3, 5)
+HG_ROW_CFG(1920,   4,    64,   16, 8, 3, 5)
+
+//          N     cols/WG  T    radices
+HG_COL_CFG(16,    16,     4,   4, 4)
+HG_COL_CFG(32,    16,     8,   4, 2, 4)
+HG_COL_CFG(64,    16,     8,   8, 8)
+HG_COL_CFG(128,   16,    16,   8, 2, 8)
+HG_COL_CFG(256,    8,    16,   16, 16)
+HG_COL_CFG(512,    4,    64,   8, 8, 8)
+HG_COL_CFG(1024,   4,    64,   16, 4, 16)
+HG_COL_CFG(2048,   4,    64,   16, 8, 16)
+HG_COL_CFG(4096,   2,   128,   16, 16, 16)
+HG_COL_CFG(24,    16,     8,   8, 3)
+HG_COL_CFG(60,    16,    16,   4, 3, 5)
+HG_COL_CFG(90,    16,    16,   2, 3, 3, 5)
+HG_COL_CFG(120,   16,    16,   8, 3, 5)
+HG_COL_CFG(1080,   4,    64,   8, 3, 3, 3, 5)
+HG_COL_CFG(1920,   4,    64,   16, 8, 3, 5)
+
+// X-macro over every compiled length (used for host dispatch tables).
+#define HG_FOR_EACH_LENGTH(X) \
+  X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
+  X(24) X(60) X(90) X(120) X(1080) X(1920)
+
+}  // namespace hg

@@ -1,0 +1,252 @@
+"""Thin Python binding of libhologen's C ABI (include/hologen.h).
+
+Argument marshalling only: every step of the hologram path runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory (tensor
+``data_ptr()``) and streams (``torch.cuda.current_stream().cuda_stream``).
+If the shared library has not been built this module raises on first use;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HG_OK = 0
+HG_ERR_INVALID_ARGUMENT = 1
+HG_ERR_UNSUPPORTED_SIZE = 2
+HG_ERR_OUT_OF_MEMORY = 3
+HG_ERR_DEVICE = 4
+HG_ERR_INTERNAL = 5
+
+HG_FOURIER = 0
+HG_FRESNEL = 1
+HG_PHASE = 0
+HG_PHASE_QUANTISED = 1
+HG_BINARY_PHASE = 2
+HG_FORWARD = 1
+HG_INVERSE = -1
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhologen.so")
+
+HG_KERNEL_GS_REPLAY = 1
+HG_KERNEL_GS_SLM = 2
+HG_KERNEL_OSPR_A = 3
+HG_KERNEL_OSPR_B = 4
+HG_KERNEL_OSPR_C = 5
+HG_KERNEL_PROP_ROW = 6
+HG_KERNEL_PROP_COL = 7
+
+EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
+            "hg_propagate", "hg_gs_iterate", "hg_ospr", "hg_timing_begin", "hg_timing_end",
+            "hg_error")
+
+
+class hg_plan_desc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("propagation", ctypes.c_int32),
+                ("wavelength", ctypes.c_double), ("pixel_pitch", ctypes.c_double),
+                ("distance", ctypes.c_double),
+                ("modulation", ctypes.c_int32), ("levels", ctypes.c_int32)]
+
+
+class HologenError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"hologen status {status}: {text}")
+        self.status = status
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libhologen.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2006_10509_amd.build`")
+    # Load torch's HIP runtime first: libhologen.so then binds to the same
+    # libamdhip64 (both carry the SONAME libamdhip64.so.7), so torch's device
+    # pointers and streams are valid in library calls.  A second runtime in the
+    # process would give the library its own device context and streams.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    _check_single_hip_runtime()
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.hg_plan_create.argtypes = [ctypes.POINTER(hg_plan_desc), ctypes.POINTER(vp)]
+    lib.hg_plan_create.restype = i32
+    lib.hg_plan_destroy.argtypes = [vp]
+    lib.hg_plan_destroy.restype = i32
+    lib.hg_workspace_bytes.argtypes = [vp]
+    lib.hg_workspace_bytes.restype = sz
+    lib.hg_length_supported.argtypes = [i32]
+    lib.hg_length_supported.restype = i32
+    lib.hg_propagate.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.hg_propagate.restype = i32
+    lib.hg_gs_iterate.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.hg_gs_iterate.restype = i32
+    lib.hg_ospr.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.hg_ospr.restype = i32
+    lib.hg_timing_begin.argtypes = [vp, i32]
+    lib.hg_timing_begin.restype = i32
+    lib.hg_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.hg_timing_end.restype = i32
+    lib.hg_error.argtypes = [i32]
+    lib.hg_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check_single_hip_runtime() -> None:
+    try:
+        with open("/proc/self/maps") as f:
+            paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return
+    real = {os.path.realpath(p) for p in paths}
+    if len(real) > 1:
+        raise RuntimeError(f"two HIP runtimes are loaded in this process: {sorted(real)}")
+
+
+def hg_error(status: int) -> str:
+    return library().hg_error(status).decode()
+
+
+def _check(status: int) -> None:
+    if status != HG_OK:
+        raise HologenError(status, hg_error(status))
+
+
+def hg_length_supported(n: int) -> bool:
+    return bool(library().hg_length_supported(n))
+
+
+# ---------------------------------------------------------------------------
+# tensor marshalling
+# ---------------------------------------------------------------------------
+
+def _ptr(t, dtype=None, shape=None, name="tensor", optional=False) -> Optional[int]:
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+@dataclass
+class Plan:
+    """Owns an hg_plan; mirrors hg_plan_desc."""
+    width: int
+    height: int
+    propagation: int = HG_FOURIER
+    wavelength: float = 0.0
+    pixel_pitch: float = 0.0
+    distance: float = 0.0
+    modulation: int = HG_PHASE
+    levels: int = 0
+
+    def __post_init__(self):
+        self._handle = hg_plan_create(self)
+
+    @property
+    def handle(self) -> int:
+        if self._handle is None:
+            raise RuntimeError("plan destroyed")
+        return self._handle
+
+    def desc(self) -> hg_plan_desc:
+        return hg_plan_desc(self.width, self.height, self.propagation, self.wavelength,
+                            self.pixel_pitch, self.distance, self.modulation, self.levels)
+
+    def workspace_bytes(self) -> int:
+        return int(library().hg_workspace_bytes(self.handle))
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes(), dtype=torch.uint8, device=device)
+
+    def destroy(self) -> None:
+        if getattr(self, "_handle", None) is not None:
+            library().hg_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hg_plan_create(spec) -> int:
+    """Create a plan from a Plan (or anything with the hg_plan_desc fields)."""
+    desc = hg_plan_desc(spec.width, spec.height, spec.propagation, spec.wavelength,
+                        spec.pixel_pitch, spec.distance, spec.modulation, spec.levels)
+    out = ctypes.c_void_p()
+    _check(library().hg_plan_create(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def hg_propagate(plan: Plan, x, out, direction: int, workspace=None, stream=None) -> None:
+    import torch
+    shape = (plan.height, plan.width)
+    _check(library().hg_propagate(plan.handle, _ptr(x, torch.complex64, shape, "in"),
+                                  _ptr(out, torch.complex64, shape, "out"), direction,
+                                  _ptr(workspace, torch.uint8, None, "workspace", optional=True),
+                                  _stream(stream)))
+
+
+def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
+                  illumination=None, levels=None, nmse=None, stream=None) -> None:
+    """In-place GS: ``phase`` holds the starting phase on entry, the result on exit."""
+    import torch
+    shape = (plan.height, plan.width)
+    _check(library().hg_gs_iterate(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape, "illumination", optional=True),
+        _ptr(phase, torch.float32, shape, "phase"),
+        _ptr(levels, torch.uint8, shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
+        int(iterations), _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+
+
+def hg_ospr(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=None,
+            nmse=None, stream=None) -> None:
+    import torch
+    shape = (plan.height, plan.width)
+    n_sub = int(sub_phase.shape[0])
+    _check(library().hg_ospr(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(sub_phase, torch.float32, (n_sub,) + shape, "sub_phase"), n_sub,
+        _ptr(holograms, torch.uint8, (n_sub,) + shape, "holograms", optional=True),
+        _ptr(intensity, torch.float32, shape, "intensity"),
+        _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
+        _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+
+
+def hg_timing_begin(plan: Plan, kernel: int) -> None:
+    _check(library().hg_timing_begin(plan.handle, kernel))
+
+
+def hg_timing_end(plan: Plan):
+    """(summed kernel milliseconds, number of timed launches)."""
+    total = ctypes.c_double()
+    count = ctypes.c_int64()
+    _check(library().hg_timing_end(plan.handle, ctypes.byref(total), ctypes.byref(count)))
+    return total.value, count.value

@@ -150,3 +150,13 @@ def test_distant_fresnel_plane_is_fourier():
     a = oracle.gs_iterate(t, phi, 6)
     b = oracle.gs_iterate(t, phi, 6, fresnel=far)
     assert np.allclose(a["nmse"], b["nmse"], rtol=1e-6, atol=0)
+
+
+def test_trace_matches_separate_runs():
+    t, phi = synthetic(24, 40, 12)
+    full = oracle.gs_iterate(t, phi, 4, levels=8, trace=True)
+    assert len(full["trace"]) == 5
+    for k in (0, 2, 4):
+        part = oracle.gs_iterate(t, phi, k, levels=8)
+        assert np.array_equal(full["trace"][k]["levels"], part["levels"])
+    assert np.array_equal(full["trace"][0]["angle"], phi)
