@@ -5,11 +5,11 @@
 // length N is carried by a team of T threads; each thread holds its share of
 // the sequence in registers, every radix-R stage is a set of R-point DFTs done
 // in registers, and the data moves between stages through LDS in Stockham
-// (self-sorting) order, so no bit-reversal pass exists.  Twiddles come from a
-// table exp(-2 pi i m / N) that the host builds in FP64 and rounds to FP32;
-// each thread copies the few entries its butterflies need into registers once
-// per kernel, before the field arrives, so no table access sits between
-// stages.
+// (self-sorting) order, so no bit-reversal pass exists.  The twiddles a thread
+// needs are evaluated on the host in FP64, rounded to FP32 and laid out per
+// thread (twiddle_image); each thread loads them into registers once per
+// kernel with coalesced loads, before the field arrives, so no table access
+// sits between stages.
 //
 // Stage s with radix R and Ns = product of the radices before it: butterfly j
 // (0 <= j < N/R) takes x[j + r N/R], r < R, multiplies by w^(r k) with
@@ -277,7 +277,11 @@ __device__ __forceinline__ void for_layout(int t, F&& f) {
 // ---------------------------------------------------------------------------
 // per-thread twiddles: stage s needs w^(r k), r = 1..R-1, for the k of each
 // butterfly the thread owns; when T is a multiple of Ns all of a thread's
-// butterflies in that stage share k.
+// butterflies in that stage share k.  Register slot i of thread t is read from
+// a twiddle image laid out [i][t] (built on the host by twiddle_image), so
+// every twiddle load is one unit-stride, coalesced wavefront load; indexing a
+// plain exp(-2 pi i m / N) table by r k would be a gather over dozens of cache
+// lines per instruction.
 // ---------------------------------------------------------------------------
 template <class P, bool REV>
 struct TwRegs {
@@ -292,23 +296,43 @@ struct TwRegs {
   static constexpr int TOTAL = offset(P::S);
   float2 w[TOTAL > 0 ? TOTAL : 1];
 
-  template <int S_>
-  __device__ __forceinline__ void load_stage(const float2* __restrict__ tw, int t) {
-    constexpr int R = P::radix(S_, REV);
-    constexpr int NS = P::ns(S_, REV);
-    constexpr int SETS = sets(S_);
-    constexpr int TWS = P::N / (NS * R);
-    constexpr int OFF = offset(S_);
+  __device__ __forceinline__ void load(const float2* __restrict__ img, int t) {
 #pragma unroll
-    for (int set = 0; set < SETS; ++set) {
-      const int k = (t + set * P::T) % NS;
-#pragma unroll
-      for (int r = 1; r < R; ++r) w[OFF + set * (R - 1) + r - 1] = tw[r * k * TWS];
-    }
-    if constexpr (S_ + 1 < P::S) load_stage<S_ + 1>(tw, t);
+    for (int i = 0; i < TOTAL; ++i) w[i] = img[i * P::T + t];
   }
-  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) { load_stage<0>(tw, t); }
+  __device__ __forceinline__ float2 at(int i, int) const { return w[i]; }
 };
+
+// The same twiddle image read from LDS at the point of use (one copy per
+// workgroup, shared by all its teams; see stage_compute).
+template <class P, bool REV>
+struct TwLds {
+  static constexpr int sets(int s) { return TwRegs<P, REV>::sets(s); }
+  static constexpr int offset(int s) { return TwRegs<P, REV>::offset(s); }
+  static constexpr int TOTAL = TwRegs<P, REV>::TOTAL;
+  const float2* img;
+  __device__ __forceinline__ float2 at(int i, int t) const { return img[i * P::T + t]; }
+};
+
+// Host: the twiddle image of order REV, TOTAL * T entries, slot i of thread t
+// at [i * T + t]: exp(-2 pi i r k / (Ns R)) evaluated in FP64.
+template <class P, bool REV>
+void twiddle_image(double* re, double* im) {
+  using TW = TwRegs<P, REV>;
+  for (int s = 0; s < P::S; ++s) {
+    const int R = P::radix(s, REV), NS = P::ns(s, REV);
+    for (int set = 0; set < TW::sets(s); ++set)
+      for (int r = 1; r < R; ++r)
+        for (int t = 0; t < P::T; ++t) {
+          const int k = (t + set * P::T) % NS;
+          const long long m = (long long)r * k;               // angle = -2 pi m / (NS R)
+          const double a = -2.0 * 3.14159265358979323846 * (double)(m % (NS * R)) / (double)(NS * R);
+          const int i = TW::offset(s) + set * (R - 1) + r - 1;
+          re[i * P::T + t] = __builtin_cos(a);
+          im[i * P::T + t] = __builtin_sin(a);
+        }
+  }
+}
 
 // One radix stage in registers: twiddle then R-point DFTs.
 template <class P, int S_, bool REV, int DIR, class TW>
@@ -327,7 +351,7 @@ __device__ __forceinline__ void stage_compute(float2* v, int t, const TW& tw) {
         const int set = SHARED ? 0 : m;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const float2 w = tw.w[OFF + set * (R - 1) + r - 1];
+          const float2 w = tw.at(OFF + set * (R - 1) + r - 1, t);
           v[m * R + r] = DIR < 0 ? cmul(v[m * R + r], w) : cmulconj(v[m * R + r], w);
         }
       }
@@ -389,5 +413,22 @@ __device__ __forceinline__ void fft_run(float2* v, int t, LdsView<MUL> lds, cons
 // palindrome (both orders have identical stages).
 template <class P, bool REV>
 using TwFor = TwRegs<P, P::PALINDROME ? false : REV>;
+
+// LDS twiddles for order REV (the forward image serves both orders of a palindrome).
+template <class P, bool REV>
+using TwLdsFor = TwLds<P, P::PALINDROME ? false : REV>;
+
+// Words of LDS taken by the twiddle images a kernel running both orders needs.
+template <class P>
+constexpr int tw_lds_len() {
+  return TwRegs<P, false>::TOTAL * P::T + (P::PALINDROME ? 0 : TwRegs<P, true>::TOTAL * P::T);
+}
+
+// Copy n complex values from global memory to LDS with every thread of the
+// workgroup (unit stride, coalesced).  The caller synchronises afterwards.
+template <int THREADS>
+__device__ __forceinline__ void lds_fill(float2* dst, const float2* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += THREADS) dst[i] = src[i];
+}
 
 }  // namespace hg

@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hologen.h"
+#include "hologen.h"
 #include "reduce.hpp"
 
 using namespace hg;
@@ -84,6 +84,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->row.gs_start, e->row.lds));
   for (auto& mode : e->row.gs_row)
     for (auto k : mode) chk(allow_lds(k, e->row.lds));
+  chk(allow_lds(e->row.gs_row_general, e->row.lds));
   chk(allow_lds(e->row.ospr_a, e->row.lds));
   chk(allow_lds(e->row.ospr_c, e->row.lds));
   chk(allow_lds(e->col.prop_fwd, e->col.lds));
@@ -105,14 +106,11 @@ std::vector<float2> to_f32(const std::vector<double>& re, const std::vector<doub
   return out;
 }
 
-// exp(-2 pi i m / n), m < n, evaluated in FP64 with the exponent reduced exactly.
-std::vector<float2> twiddles(int n) {
-  std::vector<double> re(n), im(n);
-  for (int m = 0; m < n; ++m) {
-    double a = -2.0 * M_PI * (double)m / (double)n;
-    re[m] = std::cos(a);
-    im[m] = std::sin(a);
-  }
+// A twiddle image (FP64 values from the length's kernel table) rounded to FP32.
+template <class F>
+std::vector<float2> twiddle_table(int len, F&& fill) {
+  std::vector<double> re(len > 0 ? len : 1, 1.0), im(len > 0 ? len : 1, 0.0);
+  if (len > 0) fill(re.data(), im.data());
   return to_f32(re, im);
 }
 
@@ -135,8 +133,10 @@ struct hg_plan_s {
   hg_plan_desc desc;
   const LengthEntry* row;   // kernels for rows (length = width)
   const LengthEntry* col;   // kernels for columns (length = height)
-  float2* tw_w = nullptr;   // twiddles of length width
-  float2* tw_h = nullptr;   // twiddles of length height (aliases tw_w if equal)
+  // twiddle images of the row kernels (length width) and column kernels
+  // (length height), forward and reversed radix order
+  float2* tw_row[2] = {nullptr, nullptr};
+  float2* tw_col[2] = {nullptr, nullptr};
   float2* q1y = nullptr;    // Fresnel source chirp
   float2* q1x = nullptr;
   // Fresnel propagation tables: forward pre = Q1, post = c Q2;
@@ -150,7 +150,7 @@ struct hg_plan_s {
   float2* lvl_tab = nullptr;
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
   int row_blocks = 0, col_blocks = 0;
-  size_t off_scalars = 0, off_stats = 0, off_partials = 0, ws_bytes = 0;
+  size_t off_scalars = 0, off_stats = 0, off_partials = 0, off_target = 0, ws_bytes = 0;
   std::vector<void*> allocations;
   // diagnostics: event pairs around launches of one kernel kind
   int timed_kernel = 0;
@@ -254,12 +254,14 @@ struct Workspace {
   Scalars* sc;
   double* stats;
   float* partials;
+  float* target;   // target amplitude tiled for the column pass (k_tile_target)
 };
 
 Workspace carve(hg_plan p, void* ws) {
   char* b = static_cast<char*>(ws);
   return {reinterpret_cast<float2*>(b), reinterpret_cast<Scalars*>(b + p->off_scalars),
-          reinterpret_cast<double*>(b + p->off_stats), reinterpret_cast<float*>(b + p->off_partials)};
+          reinterpret_cast<double*>(b + p->off_stats), reinterpret_cast<float*>(b + p->off_partials),
+          reinterpret_cast<float*>(b + p->off_target)};
 }
 
 size_t npix(hg_plan p) { return (size_t)p->desc.width * (size_t)p->desc.height; }
@@ -300,6 +302,7 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   if (!out) return fail(HG_ERR_INVALID_ARGUMENT, "out is NULL");
   hg_status st = validate_desc(desc);
   if (st != HG_OK) return st;
+  st = HG_OK;
   hg_plan p = new hg_plan_s();
   p->desc = *desc;
   const int W = desc->width, H = desc->height;
@@ -311,10 +314,12 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
     free_plan(p);
     return fail(HG_ERR_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
-  st = upload(p, twiddles(W), &p->tw_w);
-  if (st == HG_OK) {
-    if (H == W) p->tw_h = p->tw_w;
-    else st = upload(p, twiddles(H), &p->tw_h);
+  for (int rev = 0; rev < 2 && st == HG_OK; ++rev) {
+    st = upload(p, twiddle_table(p->row->row_tw_len[rev], [&](double* re, double* im) { p->row->row_tw(rev, re, im); }),
+                &p->tw_row[rev]);
+    if (st == HG_OK)
+      st = upload(p, twiddle_table(p->col->col_tw_len[rev], [&](double* re, double* im) { p->col->col_tw(rev, re, im); }),
+                  &p->tw_col[rev]);
   }
   if (st == HG_OK && desc->propagation == HG_FRESNEL) {
     const double lz = desc->wavelength * desc->distance;
@@ -354,7 +359,8 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   p->off_stats = p->off_scalars + align_up(sizeof(Scalars));
   p->off_partials = p->off_stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
-  p->ws_bytes = p->off_partials + align_up((size_t)kNmseChunk * nwg * sizeof(float));
+  p->off_target = p->off_partials + align_up((size_t)kNmseChunk * nwg * sizeof(float));
+  p->ws_bytes = p->off_target + align_up((size_t)p->col_blocks * p->col->col.cols * H * sizeof(float));
   *out = p;
   return HG_OK;
 }
@@ -380,11 +386,13 @@ hg_status hg_propagate(hg_plan p, const void* in_c64, void* out_c64, int32_t dir
   ra.in = static_cast<const float2*>(in_c64);
   ra.out = static_cast<float2*>(out_c64);
   ra.H = H;
-  ra.tw = p->tw_w;
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
   PropColArgs ca{};
   ca.io = static_cast<float2*>(out_c64);
   ca.W = W;
-  ca.tw = p->tw_h;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
   ca.scale = fwd ? 1.0f : (float)(1.0 / ((double)W * (double)H));
   if (fres) {
     ra.sx_in = ra.sx_out = W / 2;
@@ -434,19 +442,27 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
   ra.slm.inv_delta_f64 = p->levels ? (double)p->levels / (2.0 * M_PI) : 0.0;
   ra.slm.half_step = p->levels ? make_float2((float)std::cos(M_PI / p->levels), (float)std::sin(M_PI / p->levels))
                                : make_float2(1.0f, 0.0f);
-  ra.tw = p->tw_w;
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
+
+  const int cols = ck.cols;
+  const uint32_t tiled_n = (uint32_t)p->col_blocks * cols * H;
+  hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, target_amp, w.target, H, W, cols,
+                     tiled_n);
 
   GsColArgs ca{};
   ca.field = w.field;
   ca.W = W;
   ca.H = H;
-  ca.target = target_amp;
+  ca.target = w.target;
   ca.sc = w.sc;
-  ca.tw = p->tw_h;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
 
   const int mode = p->levels == 0 ? GS_CONT
                  : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
-  void (*gs_row)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
+  // steady-state kernel unless the pass needs illumination or produces outputs
+  void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
 
   if (nmse) enqueue_stats(p, w, target_amp, illumination, 0.0, stream);
 
@@ -475,6 +491,7 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
     if (last) break;
     ra.phase_out = k == iterations - 1 ? phase : nullptr;
     ra.levels_out = k == iterations - 1 ? levels : nullptr;
+    void (*gs_row)(GsRowArgs) = (illumination || ra.phase_out) ? rk.gs_row_general : gs_row_hot;
     launch(p, HG_KERNEL_GS_SLM, stream, [&] {
       hipLaunchKernelGGL(gs_row, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
     });
@@ -504,11 +521,13 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   ra.intensity = intensity;
   ra.inv_nsub = (float)(1.0 / (double)n_sub);
   ra.sc = w.sc;
-  ra.tw = p->tw_w;
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
   OsprColArgs ca{};
   ca.field = w.field;
   ca.W = W;
-  ca.tw = p->tw_h;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
   for (int s = 0; s < n_sub; ++s) {
     ra.theta = sub_phase + (size_t)s * n;
     ra.first = s == 0;

@@ -134,6 +134,12 @@ __device__ __forceinline__ void stg(T* base, uint32_t i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
+// Keeps the loads issued above it above it: the scheduler would otherwise sink
+// table loads into the first FFT stage, and with one wavefront per SIMD their
+// latency would then stall the second stage instead of overlapping the field
+// loads.
+__device__ __forceinline__ void issue_loads_here() { __builtin_amdgcn_sched_barrier(0); }
+
 // (i + s) mod n for 0 <= i, s < n
 template <int NC>
 __device__ __forceinline__ int wrap_add(int i, int s) {
@@ -194,6 +200,33 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 
 extern __shared__ float2 hg_dyn_lds[];
 
+// ---------------------------------------------------------------------------
+// LDS layout of a pass kernel: the teams' exchange regions, then the twiddle
+// image(s), then (row kernels) one table of N complex values such as the
+// Fresnel chirp q_x.  Tables are filled once per workgroup.
+// ---------------------------------------------------------------------------
+template <int N>
+struct RowLds {
+  using P = typename RowCfg<N>::P;
+  static constexpr int TWF = RowCfg<N>::TEAMS * lds_len(N);
+  static constexpr int TWR = P::PALINDROME ? TWF : TWF + TwRegs<P, false>::TOTAL * P::T;
+  static constexpr int TAB = TWF + tw_lds_len<P>();
+  static constexpr int WORDS = TAB + N;
+};
+template <int N>
+struct ColLds {
+  using P = typename ColCfg<N>::P;
+  static constexpr int TWF = ColCfg<N>::C * lds_len(N);
+  static constexpr int TWR = P::PALINDROME ? TWF : TWF + TwRegs<P, false>::TOTAL * P::T;
+  static constexpr int WORDS = TWF + tw_lds_len<P>();
+};
+
+template <class P, class L, int THREADS>
+__device__ __forceinline__ void fill_twiddles(const float2* tw, const float2* twr) {
+  lds_fill<THREADS>(hg_dyn_lds + L::TWF, tw, TwRegs<P, false>::TOTAL * P::T);
+  if constexpr (!P::PALINDROME) lds_fill<THREADS>(hg_dyn_lds + L::TWR, twr, TwRegs<P, true>::TOTAL * P::T);
+}
+
 // ===========================================================================
 // Propagation passes: out = post * Sh_out(FFT2(Sh_in(pre * in))), separable
 // pre/post tables and cyclic shifts (Fourier: none; Fresnel: chirps + centring).
@@ -205,13 +238,15 @@ struct PropRowArgs {
   int sx_in, sx_out;
   const float2* pre_y;  // null -> no pre-multiply
   const float2* pre_x;
-  const float2* tw;
+  const float2* tw;     // twiddle image, forward radix order
+  const float2* twr;    // twiddle image, reversed order (== tw for palindromic plans)
 };
 
 template <int N, int DIR>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
+  using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   const RowTeam<C> rt(a.H);
@@ -219,14 +254,16 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) 
   LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
+  if (a.pre_y) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.pre_x, N);
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.in, row + wrap_add<N>(x, a.sx_in)); });
-  TwFor<P, false> tw;
-  tw.load(a.tw, t);
+  issue_loads_here();
+  __syncthreads();
   if (a.pre_y) {
     const float2 py = a.pre_y[rt.y];
-    for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, ldg(a.pre_x, wrap_add<N>(x, a.sx_in)))); });
+    for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, hg_dyn_lds[LL::TAB + wrap_add<N>(x, a.sx_in)])); });
   }
-  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, tw);
+  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   if (rt.live) for_layout<L1>(t, [&](int s, int k) { stg(a.out, row + wrap_add<N>(k, a.sx_out), v[s]); });
 }
 
@@ -238,12 +275,14 @@ struct PropColArgs {
   const float2* post_x;
   float scale;
   const float2* tw;
+  const float2* twr;
 };
 
 template <int N, int DIR>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_prop_col(PropColArgs a) {
   using C = ColCfg<N>;
   using P = typename C::P;
+  using LL = ColLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
@@ -252,10 +291,11 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_prop_col(PropColArgs a) 
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)wrap_add<N>(y, a.sy_in) * a.W + x); });
-  TwFor<P, false> tw;
-  tw.load(a.tw, t);
-  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, tw);
+  issue_loads_here();
+  __syncthreads();
+  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   if (live) {
     const float2 px = a.post_y ? ldg(a.post_x, x) : make_float2(1.f, 0.f);
     for_layout<L1>(t, [&](int s, int k) {
@@ -281,6 +321,7 @@ struct GsRowArgs {
   float* phase_out;         // non-null on the pass that produces the output state
   uint8_t* levels_out;
   const float2* tw;
+  const float2* twr;
 };
 
 // SLM-constraint variants of the steady-state row pass.
@@ -304,6 +345,7 @@ template <int N>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
+  using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   const RowTeam<C> rt(a.H);
@@ -312,9 +354,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   float ph[P::REGS];
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
+  if (a.q1y) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.q1x, N);
   for_layout<L0>(t, [&](int s, int x) { ph[s] = ldg(a.phase0, row + x); });
-  TwFor<P, false> tw;
-  tw.load(a.tw, t);
+  issue_loads_here();
+  __syncthreads();
   const float2 qy = a.q1y ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   const bool out = rt.live && (a.phase_out || a.levels_out);
   for_layout<L0>(t, [&](int s, int x) {
@@ -330,10 +374,10 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
     }
     if (out) write_state(a, row + x, u, level);
     float2 h = a.illum ? cscale(u, ldg(a.illum, row + x)) : u;
-    if (a.q1y) h = cmul(h, cmul(qy, ldg(a.q1x, x)));
+    if (a.q1y) h = cmul(h, cmul(qy, hg_dyn_lds[LL::TAB + x]));
     v[s] = h;
   });
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, tw);
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
 
@@ -365,59 +409,75 @@ __device__ __forceinline__ float2 slm_constrain(float2 g, const SlmConstraint& s
   }
 }
 
-// Steady-state row pass: inverse row FFT -> conj(Q1) -> constraint -> Q1 -> row FFT.
-// The inverse runs the radices in reversed order so that its last-stage
-// register layout is the first-stage layout of the forward transform.
+// Runtime-selected constraint for the general row pass.
+__device__ __forceinline__ float2 slm_constrain_rt(float2 g, const SlmConstraint& slm, int& level) {
+  if (!slm.lvl_tab) return slm_constrain<GS_CONT>(g, slm, level);
+  if (slm.levels == 8) return slm_constrain<GS_Q8>(g, slm, level);
+  if (slm.levels == 4) return slm_constrain<GS_Q4>(g, slm, level);
+  if (slm.levels == 2) return slm_constrain<GS_Q2>(g, slm, level);
+  return slm_constrain<GS_QATAN>(g, slm, level);
+}
+
+// Row pass of a GS iteration: inverse row FFT -> conj(Q1) -> constraint -> Q1
+// -> row FFT.  The inverse runs the radices in reversed order so that its
+// last-stage register layout is the first-stage layout of the forward
+// transform.  MODE >= 0 with FRES fixed is the steady-state kernel (no
+// illumination, no outputs); MODE < 0 takes the mode, the Fresnel flag, the
+// illumination and the output arrays at run time (the pass that produces the
+// returned state, and illuminated runs).
 template <int N, int MODE, bool FRES>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
+  using LL = RowLds<N>;
   using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
   using LF = Layout<P, false, false>;  // == last stage of the reversed run
   using L1 = Layout<P, false, true>;
   static_assert(LF::R == Layout<P, true, true>::R, "layout mismatch");
+  constexpr bool GENERAL = MODE < 0;
   const RowTeam<C> rt(a.H);
   const int t = rt.t;
   LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
+  const bool fres = GENERAL ? (a.q1y != nullptr) : FRES;
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
+  if (fres) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.q1x, N);
   for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
-  TwFor<P, false> twf;
-  twf.load(a.tw, t);
-  TwFor<P, true> twi;
-  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
-  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
-    if constexpr (P::PALINDROME) return twf; else return twi;
-  }();
-  float2 q[FRES ? P::REGS : 1];
-  if constexpr (FRES) {
-    const float2 qy = a.q1y[rt.y];
-    for_layout<LF>(t, [&](int s, int x) { q[s] = cmul(qy, ldg(a.q1x, x)); });
-  }
-  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
-  auto constrain_all = [&](auto out_tag, auto illum_tag) {
-    constexpr bool OUT = decltype(out_tag)::value;
-    constexpr bool ILLUM = decltype(illum_tag)::value;
+  issue_loads_here();
+  __syncthreads();
+  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
+  const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
+  if constexpr (!GENERAL) {
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
-      if constexpr (FRES) g = cmulconj(g, q[s]);
+      float2 q;
+      if constexpr (FRES) {
+        q = cmul(qy, hg_dyn_lds[LL::TAB + x]);
+        g = cmulconj(g, q);
+      }
       int level;
       float2 u = slm_constrain<MODE>(g, a.slm, level);
-      if constexpr (OUT) write_state(a, row + x, u, level);
-      if constexpr (ILLUM) u = cscale(u, ldg(a.illum, row + x));
-      if constexpr (FRES) u = cmul(u, q[s]);
+      if constexpr (FRES) u = cmul(u, q);
       v[s] = u;
     });
-  };
-  const bool out = rt.live && (a.phase_out || a.levels_out);
-  using T_ = std::true_type;
-  using F_ = std::false_type;
-  if (out) {
-    if (a.illum) constrain_all(T_{}, T_{}); else constrain_all(T_{}, F_{});
   } else {
-    if (a.illum) constrain_all(F_{}, T_{}); else constrain_all(F_{}, F_{});
+    const bool out = rt.live && (a.phase_out || a.levels_out);
+    for_layout<LF>(t, [&](int s, int x) {
+      float2 g = v[s];
+      float2 q = make_float2(1.f, 0.f);
+      if (fres) {
+        q = cmul(qy, hg_dyn_lds[LL::TAB + x]);
+        g = cmulconj(g, q);
+      }
+      int level;
+      float2 u = slm_constrain_rt(g, a.slm, level);
+      if (out) write_state(a, row + x, u, level);
+      if (a.illum) u = cscale(u, ldg(a.illum, row + x));
+      v[s] = fres ? cmul(u, q) : u;
+    });
   }
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
 
@@ -425,10 +485,11 @@ struct GsColArgs {
   float2* field;
   int W;
   int H;
-  const float* target;        // centred target amplitude [H][W]
+  const float* target;        // target amplitude in FFT order, tiled [tile][ky][C] (k_tile_target)
   const Scalars* sc;
   float* partials;            // one float per workgroup for this state; null -> no NMSE
   const float2* tw;
+  const float2* twr;
 };
 
 // Replay-plane pass: column FFT -> R_k; NMSE partial of |R_k|^2 against T^2;
@@ -437,6 +498,7 @@ template <int N, bool REPLACE>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   using C = ColCfg<N>;
   using P = typename C::P;
+  using LL = ColLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   using LB = Layout<P, true, true>;
@@ -449,19 +511,14 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
-  // target amplitude in FFT order: T_f[ky][x] = T[(ky + H/2) % H][(x + W/2) % W]
-  const uint32_t xs = wrap_add_rt(x, a.W / 2, a.W);
   float tgt[P::REGS];
-  for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, (uint32_t)wrap_add<N>(ky, N / 2) * a.W + xs); });
-  TwFor<P, false> twf;
-  twf.load(a.tw, t);
-  TwFor<P, true> twi;
-  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
-  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
-    if constexpr (P::PALINDROME) return twf; else return twi;
-  }();
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  const uint32_t tbase = (uint32_t)tile * N * C::C + c;
+  for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, tbase + (uint32_t)ky * C::C); });
+  issue_loads_here();
+  __syncthreads();
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   float acc = 0.f;
   const bool nm = a.partials != nullptr;
   const float sa = nm ? a.sc->a : 0.f;
@@ -482,7 +539,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
     if (threadIdx.x == 0) a.partials[tile] = s;
   }
   if constexpr (REPLACE) {
-    fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
+    fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
     if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
   }
 }
@@ -501,6 +558,7 @@ struct OsprRowArgs {
   const Scalars* sc;
   float* partials;         // pass C of the last subframe: NMSE partials
   const float2* tw;
+  const float2* twr;
 };
 
 // Pass A: E = T exp(i theta) read through ifftshift -> inverse row FFT.
@@ -508,6 +566,7 @@ template <int N>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
+  using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   const RowTeam<C> rt(a.H);
@@ -516,19 +575,20 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
   float2 v[P::REGS];
   const uint32_t srow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   float th[P::REGS], am[P::REGS];
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int x) {
     const uint32_t i = srow + wrap_add<N>(x, N / 2);
     th[s] = ldg(a.theta, i);
     am[s] = ldg(a.target, i);
   });
-  TwFor<P, false> tw;
-  tw.load(a.tw, t);
+  issue_loads_here();
+  __syncthreads();
   for_layout<L0>(t, [&](int s, int) {
     float sn, cs;
     sincosf(th[s], &sn, &cs);
     v[s] = make_float2(am[s] * cs, am[s] * sn);
   });
-  fft_run<P, false, +1, C::WAVE_SYNC>(v, t, lds, tw);
+  fft_run<P, false, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   const uint32_t row = (uint32_t)rt.y * N;
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
@@ -538,6 +598,7 @@ struct OsprColArgs {
   int W;
   uint8_t* levels;   // [H][W] of this subframe, natural SLM order; may be null
   const float2* tw;
+  const float2* twr;
 };
 
 // Pass B: inverse column FFT -> h = sign(Re G) -> level -> forward column FFT of h.
@@ -545,6 +606,7 @@ template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   using C = ColCfg<N>;
   using P = typename C::P;
+  using LL = ColLds<N>;
   using LI = Layout<P, true, false>;
   using LF = Layout<P, false, false>;
   using L2 = Layout<P, false, true>;
@@ -554,22 +616,18 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
-  TwFor<P, false> twf;
-  twf.load(a.tw, t);
-  TwFor<P, true> twi;
-  if constexpr (!P::PALINDROME) twi.load(a.tw, t);
-  const TwFor<P, true>& twr = [&]() -> const TwFor<P, true>& {
-    if constexpr (P::PALINDROME) return twf; else return twi;
-  }();
-  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, twr);
+  issue_loads_here();
+  __syncthreads();
+  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
   const bool wl = live && a.levels;
   for_layout<LF>(t, [&](int s, int y) {
     const bool neg = !(v[s].x >= 0.0f);
     if (wl) stg(a.levels, (uint32_t)y * a.W + x, (uint8_t)(neg ? 1 : 0));
     v[s] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
   });
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, twf);
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
 }
 
@@ -579,6 +637,7 @@ template <int N>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
+  using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   __shared__ float red[C::THREADS / 64];
@@ -587,6 +646,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
+  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
   const uint32_t orow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   const bool nm = a.last && a.partials;
@@ -596,9 +656,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     prev[s] = a.first ? 0.0f : ldg(a.intensity, i);
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
-  TwFor<P, false> tw;
-  tw.load(a.tw, t);
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, tw);
+  issue_loads_here();
+  __syncthreads();
+  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
   float acc = 0.f;
   const float sa = nm ? a.sc->a : 0.f;
   const float sb = nm ? a.sc->b : 0.f;
@@ -624,7 +684,8 @@ struct RowKernels {
   void (*prop_fwd)(PropRowArgs);
   void (*prop_inv)(PropRowArgs);
   void (*gs_start)(GsRowArgs);
-  void (*gs_row[5][2])(GsRowArgs);   // [gs_mode_index][Fresnel]
+  void (*gs_row[5][2])(GsRowArgs);   // steady state [gs_mode_index][Fresnel]
+  void (*gs_row_general)(GsRowArgs); // outputs / illumination / any mode
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
   int teams, threads;
@@ -643,7 +704,18 @@ struct LengthEntry {
   int n;
   RowKernels row;
   ColKernels col;
+  // twiddle images (FP64 values) for the row / column launch shapes, in
+  // forward and reversed radix order; sizes in complex entries
+  int row_tw_len[2], col_tw_len[2];
+  void (*row_tw)(int rev, double* re, double* im);
+  void (*col_tw)(int rev, double* re, double* im);
 };
+
+template <class P>
+void twiddle_image_either(int rev, double* re, double* im) {
+  if (rev) twiddle_image<P, true>(re, im);
+  else twiddle_image<P, false>(re, im);
+}
 
 template <int N>
 LengthEntry make_length_entry() {
@@ -662,13 +734,22 @@ LengthEntry make_length_entry() {
   e.row.gs_row[3][1] = k_gs_row<N, GS_Q4, true>;
   e.row.gs_row[4][0] = k_gs_row<N, GS_Q8, false>;
   e.row.gs_row[4][1] = k_gs_row<N, GS_Q8, true>;
+  e.row.gs_row_general = k_gs_row<N, -1, false>;
   e.row.ospr_a = k_ospr_a<N>;
   e.row.ospr_c = k_ospr_c<N>;
   e.row.teams = RowCfg<N>::TEAMS;
   e.row.threads = RowCfg<N>::THREADS;
-  e.row.lds = sizeof(float2) * RowCfg<N>::TEAMS * lds_len(N);
+  e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, true>, k_gs_col<N, false>, k_ospr_b<N>,
-           ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColCfg<N>::C * lds_len(N)};
+           ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
+  using PR = typename RowCfg<N>::P;
+  using PC = typename ColCfg<N>::P;
+  e.row_tw_len[0] = TwRegs<PR, false>::TOTAL * PR::T;
+  e.row_tw_len[1] = TwRegs<PR, true>::TOTAL * PR::T;
+  e.col_tw_len[0] = TwRegs<PC, false>::TOTAL * PC::T;
+  e.col_tw_len[1] = TwRegs<PC, true>::TOTAL * PC::T;
+  e.row_tw = twiddle_image_either<PR>;
+  e.col_tw = twiddle_image_either<PC>;
   return e;
 }
 

@@ -11,6 +11,27 @@
 
 namespace hg {
 
+// Target amplitude rearranged once per call for the column pass: FFT order
+// (T_f[ky][kx] = T[(ky + H/2) % H][(kx + W/2) % W]) and tiled so that the C
+// columns of one column workgroup form one contiguous [ky][c] block.
+__global__ __launch_bounds__(256) void k_tile_target(const float* __restrict__ target, float* __restrict__ tiled,
+                                                     int H, int W, int C, uint32_t total) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= total) return;
+  const int c = i % C;
+  const int ky = (i / C) % H;
+  const int tile = i / (C * H);
+  const int x = tile * C + c;
+  float v = 0.0f;
+  if (x < W) {
+    const int ys = wrap_add_rt(ky, H / 2, H);
+    const int xs = wrap_add_rt(x, W / 2, W);
+    v = target[(size_t)ys * W + xs];
+  }
+  tiled[i] = v;
+}
+
+
 // ===========================================================================
 // Per-call statistics and the deterministic NMSE reduction
 // ===========================================================================
