@@ -80,7 +80,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-sample-iters", type=int, default=10)
+    ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")

@@ -141,12 +141,12 @@ hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase,
 
 /* Diagnostics: per-kernel timing with HIP events.
  * hg_timing_begin makes every later launch of `kernel` made by calls on this
- * plan record a hipEvent before and after it on the call's stream;
- * hg_timing_end waits for the last of those events, returns the summed
- * kernel time and the number of timed launches, and switches timing off.
- * The events sit between launches, so they add a small gap of their own;
- * time the plain calls separately for throughput.  A plan in timing mode
- * must be used from one host thread.
+ * plan go through hipExtLaunchKernel with a start/stop hipEvent pair, which
+ * the runtime stamps from the kernel's dispatch on the call's stream (the
+ * kernel's own duration, not the gap between launches); hg_timing_end waits
+ * for the last of those events, returns the summed kernel time and the number
+ * of timed launches, and switches timing off.  A plan in timing mode must be
+ * used from one host thread.
  * kernel: HG_KERNEL_GS_REPLAY (column pass of GS: FFT, NMSE, amplitude
  * replacement, inverse FFT), HG_KERNEL_GS_SLM (row pass of GS: inverse FFT,
  * SLM constraint, FFT), HG_KERNEL_OSPR_A / _B / _C (the three OSPR passes),

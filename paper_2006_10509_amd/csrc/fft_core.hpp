@@ -418,6 +418,24 @@ using TwFor = TwRegs<P, P::PALINDROME ? false : REV>;
 template <class P, bool REV>
 using TwLdsFor = TwLds<P, P::PALINDROME ? false : REV>;
 
+// Twiddle registers worth holding for a whole transform: up to 16 complex
+// values (32 VGPRs).  Larger sets stay in LDS and are read at each use, since
+// holding them would push the transform's registers into AGPR spills.
+constexpr int TW_REG_MAX = 16;
+
+// Full transform of order REV with twiddles from the workgroup's LDS image:
+// copied into registers once when the set is small, else read where used.
+template <class P, bool REV, int DIR, bool WAVE_SYNC, int MUL>
+__device__ __forceinline__ void fft_run_lds_tw(float2* v, int t, LdsView<MUL> lds, const float2* img) {
+  if constexpr (TwFor<P, REV>::TOTAL <= TW_REG_MAX) {
+    TwFor<P, REV> tw;
+    tw.load(img, t);
+    fft_run<P, REV, DIR, WAVE_SYNC>(v, t, lds, tw);
+  } else {
+    fft_run<P, REV, DIR, WAVE_SYNC>(v, t, lds, TwLdsFor<P, REV>{img});
+  }
+}
+
 // Words of LDS taken by the twiddle images a kernel running both orders needs.
 template <class P>
 constexpr int tw_lds_len() {

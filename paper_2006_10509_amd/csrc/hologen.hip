@@ -7,6 +7,7 @@
 // copies (Sec. 7.3; Sec. 4, Algorithm Interface); here the large images stay
 // caller-owned device buffers and the plan keeps only small constant tables.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <complex>
@@ -183,32 +184,37 @@ void free_plan(hg_plan p) {
   delete p;
 }
 
-// Launch helper: brackets the launch with timing events when `kind` is timed.
-template <class F>
-void launch(hg_plan p, int kind, hipStream_t s, F&& f) {
-  const bool timed = p->timed_kernel == kind && p->ev_error == hipSuccess;
-  if (timed) {
-    if (p->ev_used == p->ev_start.size()) {
-      hipEvent_t a = nullptr, b = nullptr;
-      hipError_t e = hipEventCreate(&a);
-      if (e == hipSuccess) e = hipEventCreate(&b);
-      if (e != hipSuccess) {
-        p->ev_error = e;
-        f();
-        return;
-      }
-      p->ev_start.push_back(a);
-      p->ev_stop.push_back(b);
+// Launch helper.  When `kind` is the timed kernel the launch goes through
+// hipExtLaunchKernel with a start/stop event pair: the runtime stamps the pair
+// from the dispatch itself, so the elapsed time is the kernel's own duration
+// (first wave start to last wave end), without the gap between launches.
+template <class A>
+void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, int threads, size_t lds, A& args) {
+  if (p->timed_kernel != kind || p->ev_error != hipSuccess) {
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+    return;
+  }
+  if (p->ev_used == p->ev_start.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      p->ev_error = e;
+      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+      return;
     }
-    hipError_t e = hipEventRecord(p->ev_start[p->ev_used], s);
-    if (e != hipSuccess) p->ev_error = e;
+    p->ev_start.push_back(a);
+    p->ev_stop.push_back(b);
   }
-  f();
-  if (timed && p->ev_error == hipSuccess) {
-    hipError_t e = hipEventRecord(p->ev_stop[p->ev_used], s);
-    if (e != hipSuccess) p->ev_error = e;
-    ++p->ev_used;
+  void* argv[] = {&args};
+  hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(threads), argv, lds, s,
+                                    p->ev_start[p->ev_used], p->ev_stop[p->ev_used], 0);
+  if (e != hipSuccess) {
+    p->ev_error = e;
+    return;
   }
+  ++p->ev_used;
 }
 
 hg_status validate_desc(const hg_plan_desc* d) {
@@ -407,12 +413,8 @@ hg_status hg_propagate(hg_plan p, const void* in_c64, void* out_c64, int32_t dir
   }
   const RowKernels& rk = p->row->row;
   const ColKernels& ck = p->col->col;
-  launch(p, HG_KERNEL_PROP_ROW, stream, [&] {
-    hipLaunchKernelGGL(fwd ? rk.prop_fwd : rk.prop_inv, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
-  });
-  launch(p, HG_KERNEL_PROP_COL, stream, [&] {
-    hipLaunchKernelGGL(fwd ? ck.prop_fwd : ck.prop_inv, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
-  });
+  launch(p, HG_KERNEL_PROP_ROW, stream, fwd ? rk.prop_fwd : rk.prop_inv, p->row_blocks, rk.threads, rk.lds, ra);
+  launch(p, HG_KERNEL_PROP_COL, stream, fwd ? ck.prop_fwd : ck.prop_inv, p->col_blocks, ck.threads, ck.lds, ca);
   return launch_status("hg_propagate launch");
 }
 
@@ -479,9 +481,7 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
     if (last) {
       hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
     } else {
-      launch(p, HG_KERNEL_GS_REPLAY, stream, [&] {
-        hipLaunchKernelGGL(ck.gs_col, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
-      });
+      launch(p, HG_KERNEL_GS_REPLAY, stream, ck.gs_col, p->col_blocks, ck.threads, ck.lds, ca);
     }
     if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
       hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream, w.partials,
@@ -492,9 +492,7 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
     ra.phase_out = k == iterations - 1 ? phase : nullptr;
     ra.levels_out = k == iterations - 1 ? levels : nullptr;
     void (*gs_row)(GsRowArgs) = (illumination || ra.phase_out) ? rk.gs_row_general : gs_row_hot;
-    launch(p, HG_KERNEL_GS_SLM, stream, [&] {
-      hipLaunchKernelGGL(gs_row, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
-    });
+    launch(p, HG_KERNEL_GS_SLM, stream, gs_row, p->row_blocks, rk.threads, rk.lds, ra);
   }
   return launch_status("hg_gs_iterate launch");
 }
@@ -534,15 +532,9 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     ra.last = s == n_sub - 1;
     ra.partials = (ra.last && nmse) ? w.partials : nullptr;
     ca.levels = holograms ? holograms + (size_t)s * n : nullptr;
-    launch(p, HG_KERNEL_OSPR_A, stream, [&] {
-      hipLaunchKernelGGL(rk.ospr_a, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
-    });
-    launch(p, HG_KERNEL_OSPR_B, stream, [&] {
-      hipLaunchKernelGGL(ck.ospr_b, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
-    });
-    launch(p, HG_KERNEL_OSPR_C, stream, [&] {
-      hipLaunchKernelGGL(rk.ospr_c, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
-    });
+    launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
+    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b, p->col_blocks, ck.threads, ck.lds, ca);
+    launch(p, HG_KERNEL_OSPR_C, stream, rk.ospr_c, p->row_blocks, rk.threads, rk.lds, ra);
   }
   if (nmse)
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, w.partials, p->row_blocks,

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) 
     const float2 py = a.pre_y[rt.y];
     for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, hg_dyn_lds[LL::TAB + wrap_add<N>(x, a.sx_in)])); });
   }
-  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, DIR, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   if (rt.live) for_layout<L1>(t, [&](int s, int k) { stg(a.out, row + wrap_add<N>(k, a.sx_out), v[s]); });
 }
 
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_prop_col(PropColArgs a) 
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)wrap_add<N>(y, a.sy_in) * a.W + x); });
   issue_loads_here();
   __syncthreads();
-  fft_run<P, false, DIR, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, DIR, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   if (live) {
     const float2 px = a.post_y ? ldg(a.post_x, x) : make_float2(1.f, 0.f);
     for_layout<L1>(t, [&](int s, int k) {
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
     if (a.q1y) h = cmul(h, cmul(qy, hg_dyn_lds[LL::TAB + x]));
     v[s] = h;
   });
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
 
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
   issue_loads_here();
   __syncthreads();
-  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
+  fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   if constexpr (!GENERAL) {
     for_layout<LF>(t, [&](int s, int x) {
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       v[s] = fres ? cmul(u, q) : u;
     });
   }
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
 
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, tbase + (uint32_t)ky * C::C); });
   issue_loads_here();
   __syncthreads();
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   float acc = 0.f;
   const bool nm = a.partials != nullptr;
   const float sa = nm ? a.sc->a : 0.f;
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
     if (threadIdx.x == 0) a.partials[tile] = s;
   }
   if constexpr (REPLACE) {
-    fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
+    fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
     if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
   }
 }
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
     sincosf(th[s], &sn, &cs);
     v[s] = make_float2(am[s] * cs, am[s] * sn);
   });
-  fft_run<P, false, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   const uint32_t row = (uint32_t)rt.y * N;
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
@@ -620,14 +620,14 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
   issue_loads_here();
   __syncthreads();
-  fft_run<P, true, +1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, true>{hg_dyn_lds + LL::TWR});
+  fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
   const bool wl = live && a.levels;
   for_layout<LF>(t, [&](int s, int y) {
     const bool neg = !(v[s].x >= 0.0f);
     if (wl) stg(a.levels, (uint32_t)y * a.W + x, (uint8_t)(neg ? 1 : 0));
     v[s] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
   });
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
 }
 
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   });
   issue_loads_here();
   __syncthreads();
-  fft_run<P, false, -1, C::WAVE_SYNC>(v, t, lds, TwLdsFor<P, false>{hg_dyn_lds + LL::TWF});
+  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
   float acc = 0.f;
   const float sa = nm ? a.sc->a : 0.f;
   const float sb = nm ? a.sc->b : 0.f;

@@ -37,7 +37,7 @@ HG_ROW_CFG(64,    32,     8,   8, 8)
 HG_ROW_CFG(128,   16,    16,   8, 2, 8)
 HG_ROW_CFG(256,   16,    16,   16, 16)
 HG_ROW_CFG(512,    4,    64,   8, 8, 8)
-HG_ROW_CFG(1024,   4,    64,   16, 4, 16)
+HG_ROW_CFG(1024,   2,   128,   8, 4, 4, 8)
 HG_ROW_CFG(2048,   2,    64,   16, 8, 16)
 HG_ROW_CFG(4096,   2,   128,   16, 16, 16)
 HG_ROW_CFG(24,    32,     8,   8, 3)
@@ -54,7 +54,7 @@ HG_COL_CFG(64,    16,     8,   8, 8)
 HG_COL_CFG(128,   16,    16,   8, 2, 8)
 HG_COL_CFG(256,    8,    16,   16, 16)
 HG_COL_CFG(512,    4,    64,   8, 8, 8)
-HG_COL_CFG(1024,   4,    64,   16, 4, 16)
+HG_COL_CFG(1024,   4,   128,   8, 4, 4, 8)
 HG_COL_CFG(2048,   4,    64,   16, 8, 16)
 HG_COL_CFG(4096,   2,   128,   16, 16, 16)
 HG_COL_CFG(24,    16,     8,   8, 3)
