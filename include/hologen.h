@@ -141,19 +141,31 @@ hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase,
 
 /* Diagnostics: per-kernel timing with HIP events.
  * hg_timing_begin makes every later launch of `kernel` made by calls on this
- * plan go through hipExtLaunchKernel with a start/stop hipEvent pair, which
- * the runtime stamps from the kernel's dispatch on the call's stream (the
- * kernel's own duration, not the gap between launches); hg_timing_end waits
- * for the last of those events, returns the summed kernel time and the number
- * of timed launches, and switches timing off.  A plan in timing mode must be
- * used from one host thread.
+ * plan a timed launch on the call's stream, until hg_timing_end.
+ * repeats == 1: the launch goes through hipExtLaunchKernel with a start/stop
+ *   hipEvent pair that the runtime stamps from the dispatch itself.  Results
+ *   are unchanged, but attaching the events costs the timed kernel about
+ *   0.5-1 us of its own and shifts cache write-back work between it and the
+ *   next kernel, so this mode overstates short kernels.
+ * repeats > 1: the kernel is launched `repeats` times back to back with
+ *   identical arguments, one hipEventRecord before the first and one after
+ *   the last, so the average is the kernel's duration plus the small gap
+ *   between back-to-back dispatches, with nothing attached to any launch.
+ *   Every repeat rewrites the kernel's outputs from its inputs, so the
+ *   numbers a call returns in this mode are not its results: use it for
+ *   timing only.
+ * hg_timing_end waits for the last event, returns the summed kernel time and
+ * the number of kernel executions it covers (launches x repeats), and
+ * switches timing off.  A plan in timing mode must be used from one host
+ * thread.  Errors: HG_ERR_INVALID_ARGUMENT for an unknown kernel id or
+ * repeats outside 1..1000.
  * kernel: HG_KERNEL_GS_REPLAY (column pass of GS: FFT, NMSE, amplitude
  * replacement, inverse FFT), HG_KERNEL_GS_SLM (row pass of GS: inverse FFT,
  * SLM constraint, FFT), HG_KERNEL_OSPR_A / _B / _C (the three OSPR passes),
  * HG_KERNEL_PROP_ROW / _COL (hg_propagate passes). */
 enum { HG_KERNEL_GS_REPLAY = 1, HG_KERNEL_GS_SLM = 2, HG_KERNEL_OSPR_A = 3, HG_KERNEL_OSPR_B = 4,
        HG_KERNEL_OSPR_C = 5, HG_KERNEL_PROP_ROW = 6, HG_KERNEL_PROP_COL = 7 };
-hg_status hg_timing_begin(hg_plan plan, int32_t kernel);
+hg_status hg_timing_begin(hg_plan plan, int32_t kernel, int32_t repeats);
 hg_status hg_timing_end(hg_plan plan, double* total_ms, int64_t* launches);
 
 /* Static text for a status.  If s equals the calling thread's last non-OK

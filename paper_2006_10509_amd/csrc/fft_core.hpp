@@ -442,11 +442,80 @@ constexpr int tw_lds_len() {
   return TwRegs<P, false>::TOTAL * P::T + (P::PALINDROME ? 0 : TwRegs<P, true>::TOTAL * P::T);
 }
 
-// Copy n complex values from global memory to LDS with every thread of the
-// workgroup (unit stride, coalesced).  The caller synchronises afterwards.
-template <int THREADS>
-__device__ __forceinline__ void lds_fill(float2* dst, const float2* __restrict__ src, int n) {
-  for (int i = threadIdx.x; i < n; i += THREADS) dst[i] = src[i];
+// Copy N_ complex values from global memory to LDS with every thread of the
+// workgroup (unit stride, coalesced).  Each thread issues its loads in batches
+// of 8 before writing any of them, so a batch costs one memory round trip.
+// The caller synchronises afterwards.
+template <int THREADS, int N_>
+__device__ __forceinline__ void lds_fill(float2* dst, const float2* __restrict__ src) {
+  constexpr int PER = (N_ + THREADS - 1) / THREADS, B = 8;
+#pragma unroll
+  for (int b = 0; b < PER; b += B) {
+    float2 tmp[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int i = (b + j) * THREADS + (int)threadIdx.x;
+      if (b + j < PER && i < N_) tmp[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int i = (b + j) * THREADS + (int)threadIdx.x;
+      if (b + j < PER && i < N_) dst[i] = tmp[j];
+    }
+  }
 }
+
+// Twiddles of one pass kernel for the transform orders it runs (USE_F: the
+// forward radix order, USE_R: the reversed one).  When every set it needs
+// holds at most TW_REG_MAX values per thread, each thread loads its own
+// entries from the global twiddle image straight into registers: coalesced
+// loads that go out with the kernel's data loads and need neither LDS nor a
+// barrier.  Larger sets are copied into the workgroup's LDS at `lds_img`
+// (visible after the caller's barrier) and read from there.
+template <class P, int THREADS, bool USE_F, bool USE_R>
+struct PassTwiddles {
+  static constexpr bool PAL = P::PALINDROME;
+  static constexpr bool NEED_F = USE_F || (USE_R && PAL);  // a palindrome runs both orders on the forward set
+  static constexpr bool NEED_R = USE_R && !PAL;
+  static constexpr int LEN_F = TwRegs<P, false>::TOTAL * P::T;
+  static constexpr int LEN_R = TwRegs<P, true>::TOTAL * P::T;
+  static constexpr bool IN_REGS = (!NEED_F || TwRegs<P, false>::TOTAL <= TW_REG_MAX) &&
+                                  (!NEED_R || TwRegs<P, true>::TOTAL <= TW_REG_MAX);
+  // true when begin() writes LDS and the caller must barrier before run()
+  static constexpr bool USES_LDS = !IN_REGS;
+  // LDS words the twiddles take (0 in register mode)
+  static constexpr int LDS_WORDS = IN_REGS ? 0 : (NEED_F ? LEN_F : 0) + (NEED_R ? LEN_R : 0);
+
+  TwRegs<P, false> f;
+  TwRegs<P, true> r;
+  const float2* img_f = nullptr;
+  const float2* img_r = nullptr;
+
+  __device__ __forceinline__ void begin(const float2* tw, const float2* twr, float2* lds_img, int t) {
+    if constexpr (IN_REGS) {
+      if constexpr (NEED_F) f.load(tw, t);
+      if constexpr (NEED_R) r.load(twr, t);
+    } else {
+      float2* rimg = lds_img + (NEED_F ? LEN_F : 0);
+      if constexpr (NEED_F) lds_fill<THREADS, LEN_F>(lds_img, tw);
+      if constexpr (NEED_R) lds_fill<THREADS, LEN_R>(rimg, twr);
+      img_f = lds_img;
+      img_r = rimg;
+    }
+  }
+
+  // Full transform of order REV (see fft_run).
+  template <bool REV, int DIR, bool WAVE_SYNC, int MUL>
+  __device__ __forceinline__ void run(float2* v, int t, LdsView<MUL> lds) const {
+    static_assert(REV ? USE_R : USE_F, "order not loaded");
+    constexpr bool OWN_R = REV && !PAL;
+    if constexpr (IN_REGS) {
+      if constexpr (OWN_R) fft_run<P, true, DIR, WAVE_SYNC>(v, t, lds, r);
+      else fft_run<P, REV, DIR, WAVE_SYNC>(v, t, lds, f);
+    } else {
+      fft_run_lds_tw<P, REV, DIR, WAVE_SYNC>(v, t, lds, OWN_R ? img_r : img_f);
+    }
+  }
+};
 
 }  // namespace hg

@@ -155,8 +155,10 @@ struct hg_plan_s {
   std::vector<void*> allocations;
   // diagnostics: event pairs around launches of one kernel kind
   int timed_kernel = 0;
+  int timed_repeats = 1;
   std::vector<hipEvent_t> ev_start, ev_stop;
   size_t ev_used = 0;
+  int64_t timed_runs = 0;
   hipError_t ev_error = hipSuccess;
 };
 
@@ -184,10 +186,10 @@ void free_plan(hg_plan p) {
   delete p;
 }
 
-// Launch helper.  When `kind` is the timed kernel the launch goes through
-// hipExtLaunchKernel with a start/stop event pair: the runtime stamps the pair
-// from the dispatch itself, so the elapsed time is the kernel's own duration
-// (first wave start to last wave end), without the gap between launches.
+// Launch helper.  When `kind` is the timed kernel: with one repeat the launch
+// goes through hipExtLaunchKernel with a start/stop event pair stamped from
+// the dispatch itself; with R > 1 repeats the kernel is launched R times back
+// to back between two hipEventRecord calls (see hg_timing_begin).
 template <class A>
 void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, int threads, size_t lds, A& args) {
   if (p->timed_kernel != kind || p->ev_error != hipSuccess) {
@@ -207,14 +209,25 @@ void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, i
     p->ev_start.push_back(a);
     p->ev_stop.push_back(b);
   }
-  void* argv[] = {&args};
-  hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(threads), argv, lds, s,
-                                    p->ev_start[p->ev_used], p->ev_stop[p->ev_used], 0);
+  hipEvent_t a = p->ev_start[p->ev_used], b = p->ev_stop[p->ev_used];
+  hipError_t e = hipSuccess;
+  if (p->timed_repeats == 1) {
+    void* argv[] = {&args};
+    e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(threads), argv, lds, s, a, b, 0);
+  } else {
+    e = hipEventRecord(a, s);
+    for (int r = 0; e == hipSuccess && r < p->timed_repeats; ++r) {
+      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+  }
   if (e != hipSuccess) {
     p->ev_error = e;
     return;
   }
   ++p->ev_used;
+  p->timed_runs += p->timed_repeats;
 }
 
 hg_status validate_desc(const hg_plan_desc* d) {
@@ -542,12 +555,15 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   return launch_status("hg_ospr launch");
 }
 
-hg_status hg_timing_begin(hg_plan p, int32_t kernel) {
+hg_status hg_timing_begin(hg_plan p, int32_t kernel, int32_t repeats) {
   if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (kernel < HG_KERNEL_GS_REPLAY || kernel > HG_KERNEL_PROP_COL)
     return fail(HG_ERR_INVALID_ARGUMENT, "unknown kernel id");
+  if (repeats < 1 || repeats > 1000) return fail(HG_ERR_INVALID_ARGUMENT, "repeats must be in 1..1000");
   p->timed_kernel = kernel;
+  p->timed_repeats = repeats;
   p->ev_used = 0;
+  p->timed_runs = 0;
   p->ev_error = hipSuccess;
   return HG_OK;
 }
@@ -556,9 +572,12 @@ hg_status hg_timing_end(hg_plan p, double* total_ms, int64_t* launches) {
   if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (!total_ms || !launches) return fail(HG_ERR_INVALID_ARGUMENT, "total_ms/launches is NULL");
   const size_t used = p->ev_used;
+  const int64_t runs = p->timed_runs;
   const hipError_t pending = p->ev_error;
   p->timed_kernel = 0;
+  p->timed_repeats = 1;
   p->ev_used = 0;
+  p->timed_runs = 0;
   p->ev_error = hipSuccess;
   if (pending != hipSuccess) return fail(HG_ERR_DEVICE, std::string("timing events: ") + hipGetErrorString(pending));
   double sum = 0.0;
@@ -573,7 +592,7 @@ hg_status hg_timing_end(hg_plan p, double* total_ms, int64_t* launches) {
     }
   }
   *total_ms = sum;
-  *launches = (int64_t)used;
+  *launches = runs;
   return HG_OK;
 }
 

@@ -134,6 +134,34 @@ __device__ __forceinline__ void stg(T* base, uint32_t i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
+// Field accesses of the GS passes of length N.  For N <= 1024 they carry the
+// nontemporal hint (each pass reads and writes the field once; measured on the
+// 1024^2 loop it saves about 2 % per iteration).  Longer passes use plain
+// accesses: at 2048^2 the hint made a column pass, whose 32-byte row segments
+// neighbouring workgroups share through L2, 1.5x slower, and on a row pass's
+// stores it slowed the following column pass by about 10 %.  The propagation
+// and OSPR passes use plain accesses throughout.
+template <int N>
+__device__ __forceinline__ float2 ldg_field(const float2* base, uint32_t i) {
+  if constexpr (N <= 1024) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v w = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(reinterpret_cast<const char*>(base) + i * 8u));
+    return make_float2(w.x, w.y);
+  } else {
+    return ldg(base, i);
+  }
+}
+template <int N>
+__device__ __forceinline__ void stg_field(float2* base, uint32_t i, float2 v) {
+  if constexpr (N <= 1024) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(reinterpret_cast<char*>(base) + i * 8u));
+  } else {
+    stg(base, i, v);
+  }
+}
+
 // Keeps the loads issued above it above it: the scheduler would otherwise sink
 // table loads into the first FFT stage, and with one wavefront per SIMD their
 // latency would then stall the second stage instead of overlapping the field
@@ -202,30 +230,46 @@ extern __shared__ float2 hg_dyn_lds[];
 
 // ---------------------------------------------------------------------------
 // LDS layout of a pass kernel: the teams' exchange regions, then the twiddle
-// image(s), then (row kernels) one table of N complex values such as the
-// Fresnel chirp q_x.  Tables are filled once per workgroup.
+// images when they are too large for registers (see PassTwiddles), then (row
+// kernels) one table of N complex values such as the Fresnel chirp q_x when it
+// is shared through LDS (see RowTable).
 // ---------------------------------------------------------------------------
 template <int N>
 struct RowLds {
-  using P = typename RowCfg<N>::P;
-  static constexpr int TWF = RowCfg<N>::TEAMS * lds_len(N);
-  static constexpr int TWR = P::PALINDROME ? TWF : TWF + TwRegs<P, false>::TOTAL * P::T;
-  static constexpr int TAB = TWF + tw_lds_len<P>();
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  static constexpr int TWF = C::TEAMS * lds_len(N);
+  static constexpr int TAB = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
   static constexpr int WORDS = TAB + N;
 };
 template <int N>
 struct ColLds {
-  using P = typename ColCfg<N>::P;
-  static constexpr int TWF = ColCfg<N>::C * lds_len(N);
-  static constexpr int TWR = P::PALINDROME ? TWF : TWF + TwRegs<P, false>::TOTAL * P::T;
-  static constexpr int WORDS = TWF + tw_lds_len<P>();
+  using C = ColCfg<N>;
+  using P = typename C::P;
+  static constexpr int TWF = C::C * lds_len(N);
+  static constexpr int WORDS = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
 };
 
-template <class P, class L, int THREADS>
-__device__ __forceinline__ void fill_twiddles(const float2* tw, const float2* twr) {
-  lds_fill<THREADS>(hg_dyn_lds + L::TWF, tw, TwRegs<P, false>::TOTAL * P::T);
-  if constexpr (!P::PALINDROME) lds_fill<THREADS>(hg_dyn_lds + L::TWR, twr, TwRegs<P, true>::TOTAL * P::T);
-}
+// Per-column table of a row pass (the Fresnel chirp q_x), read at the
+// positions of layout L.  With at most 16 register slots per thread, each
+// thread loads its own entries straight from global memory together with the
+// field; larger layouts share one LDS copy per workgroup, visible after the
+// caller's barrier.
+template <int N, class L>
+struct RowTable {
+  using P = typename RowCfg<N>::P;
+  static constexpr bool IN_REGS = P::REGS <= 16;
+  static constexpr bool USES_LDS = !IN_REGS;
+  float2 r[IN_REGS ? P::REGS : 1];
+  __device__ __forceinline__ void begin(const float2* src, int t) {
+    if constexpr (IN_REGS) for_layout<L>(t, [&](int s, int x) { r[s] = src[x]; });
+    else lds_fill<RowCfg<N>::THREADS, N>(hg_dyn_lds + RowLds<N>::TAB, src);
+  }
+  __device__ __forceinline__ float2 at(int s, int x) const {
+    if constexpr (IN_REGS) return r[s];
+    else return hg_dyn_lds[RowLds<N>::TAB + x];
+  }
+};
 
 // ===========================================================================
 // Propagation passes: out = post * Sh_out(FFT2(Sh_in(pre * in))), separable
@@ -254,16 +298,17 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) 
   LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
-  if (a.pre_y) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.pre_x, N);
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.in, row + wrap_add<N>(x, a.sx_in)); });
   issue_loads_here();
+  PassTwiddles<P, C::THREADS, true, false> tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if (a.pre_y) lds_fill<C::THREADS, N>(hg_dyn_lds + LL::TAB, a.pre_x);
   __syncthreads();
   if (a.pre_y) {
     const float2 py = a.pre_y[rt.y];
     for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, hg_dyn_lds[LL::TAB + wrap_add<N>(x, a.sx_in)])); });
   }
-  fft_run_lds_tw<P, false, DIR, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  tw.template run<false, DIR, C::WAVE_SYNC>(v, t, lds);
   if (rt.live) for_layout<L1>(t, [&](int s, int k) { stg(a.out, row + wrap_add<N>(k, a.sx_out), v[s]); });
 }
 
@@ -291,11 +336,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_prop_col(PropColArgs a) 
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)wrap_add<N>(y, a.sy_in) * a.W + x); });
   issue_loads_here();
-  __syncthreads();
-  fft_run_lds_tw<P, false, DIR, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<false, DIR, C::WAVE_SYNC>(v, t, lds);
   if (live) {
     const float2 px = a.post_y ? ldg(a.post_x, x) : make_float2(1.f, 0.f);
     for_layout<L1>(t, [&](int s, int k) {
@@ -354,11 +401,15 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   float ph[P::REGS];
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
-  if (a.q1y) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.q1x, N);
   for_layout<L0>(t, [&](int s, int x) { ph[s] = ldg(a.phase0, row + x); });
   issue_loads_here();
-  __syncthreads();
+  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  using QX = RowTable<N, L0>;
+  TW tw;
+  QX qx;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if (a.q1y) qx.begin(a.q1x, t);
+  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
   const float2 qy = a.q1y ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   const bool out = rt.live && (a.phase_out || a.levels_out);
   for_layout<L0>(t, [&](int s, int x) {
@@ -374,11 +425,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
     }
     if (out) write_state(a, row + x, u, level);
     float2 h = a.illum ? cscale(u, ldg(a.illum, row + x)) : u;
-    if (a.q1y) h = cmul(h, cmul(qy, hg_dyn_lds[LL::TAB + x]));
+    if (a.q1y) h = cmul(h, cmul(qy, qx.at(s, x)));
     v[s] = h;
   });
-  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
-  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, row + x, v[s]); });
 }
 
 // exp(i o pi / 4) for an octant index o in [0, 8), from the index bits: the
@@ -441,19 +492,23 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   const bool fres = GENERAL ? (a.q1y != nullptr) : FRES;
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
-  if (fres) lds_fill<C::THREADS>(hg_dyn_lds + LL::TAB, a.q1x, N);
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, row + x); });
   issue_loads_here();
-  __syncthreads();
-  fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
+  using TW = PassTwiddles<P, C::THREADS, true, true>;
+  using QX = RowTable<N, LF>;
+  TW tw;
+  QX qx;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if (fres) qx.begin(a.q1x, t);
+  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   if constexpr (!GENERAL) {
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
       float2 q;
       if constexpr (FRES) {
-        q = cmul(qy, hg_dyn_lds[LL::TAB + x]);
+        q = cmul(qy, qx.at(s, x));
         g = cmulconj(g, q);
       }
       int level;
@@ -467,7 +522,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       float2 g = v[s];
       float2 q = make_float2(1.f, 0.f);
       if (fres) {
-        q = cmul(qy, hg_dyn_lds[LL::TAB + x]);
+        q = cmul(qy, qx.at(s, x));
         g = cmulconj(g, q);
       }
       int level;
@@ -477,8 +532,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       v[s] = fres ? cmul(u, q) : u;
     });
   }
-  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
-  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, row + x, v[s]); });
 }
 
 struct GsColArgs {
@@ -511,14 +566,16 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
-  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.field, (uint32_t)y * a.W + x); });
   float tgt[P::REGS];
   const uint32_t tbase = (uint32_t)tile * N * C::C + c;
   for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, tbase + (uint32_t)ky * C::C); });
   issue_loads_here();
-  __syncthreads();
-  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  using TW = PassTwiddles<P, C::THREADS, true, REPLACE>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   float acc = 0.f;
   const bool nm = a.partials != nullptr;
   const float sa = nm ? a.sc->a : 0.f;
@@ -539,8 +596,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
     if (threadIdx.x == 0) a.partials[tile] = s;
   }
   if constexpr (REPLACE) {
-    fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
-    if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
+    tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+    if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, (uint32_t)y * a.W + x, v[s]); });
   }
 }
 
@@ -575,20 +632,22 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
   float2 v[P::REGS];
   const uint32_t srow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   float th[P::REGS], am[P::REGS];
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int x) {
     const uint32_t i = srow + wrap_add<N>(x, N / 2);
     th[s] = ldg(a.theta, i);
     am[s] = ldg(a.target, i);
   });
   issue_loads_here();
-  __syncthreads();
+  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
   for_layout<L0>(t, [&](int s, int) {
     float sn, cs;
     sincosf(th[s], &sn, &cs);
     v[s] = make_float2(am[s] * cs, am[s] * sn);
   });
-  fft_run_lds_tw<P, false, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  tw.template run<false, +1, C::WAVE_SYNC>(v, t, lds);
   const uint32_t row = (uint32_t)rt.y * N;
   if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
 }
@@ -616,18 +675,20 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
   issue_loads_here();
-  __syncthreads();
-  fft_run_lds_tw<P, true, +1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWR);
+  using TW = PassTwiddles<P, C::THREADS, true, true>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const bool wl = live && a.levels;
   for_layout<LF>(t, [&](int s, int y) {
     const bool neg = !(v[s].x >= 0.0f);
     if (wl) stg(a.levels, (uint32_t)y * a.W + x, (uint8_t)(neg ? 1 : 0));
     v[s] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
   });
-  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
 }
 
@@ -646,7 +707,6 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
-  fill_twiddles<P, LL, C::THREADS>(a.tw, a.twr);
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
   const uint32_t orow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   const bool nm = a.last && a.partials;
@@ -657,8 +717,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
   issue_loads_here();
-  __syncthreads();
-  fft_run_lds_tw<P, false, -1, C::WAVE_SYNC>(v, t, lds, hg_dyn_lds + LL::TWF);
+  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   float acc = 0.f;
   const float sa = nm ? a.sc->a : 0.f;
   const float sb = nm ? a.sc->b : 0.f;

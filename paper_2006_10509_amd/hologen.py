@@ -89,7 +89,7 @@ def library() -> ctypes.CDLL:
     lib.hg_gs_iterate.restype = i32
     lib.hg_ospr.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr.restype = i32
-    lib.hg_timing_begin.argtypes = [vp, i32]
+    lib.hg_timing_begin.argtypes = [vp, i32, i32]
     lib.hg_timing_begin.restype = i32
     lib.hg_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.hg_timing_end.restype = i32
@@ -240,12 +240,12 @@ def hg_ospr(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=N
         _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
 
 
-def hg_timing_begin(plan: Plan, kernel: int) -> None:
-    _check(library().hg_timing_begin(plan.handle, kernel))
+def hg_timing_begin(plan: Plan, kernel: int, repeats: int = 1) -> None:
+    _check(library().hg_timing_begin(plan.handle, kernel, repeats))
 
 
 def hg_timing_end(plan: Plan):
-    """(summed kernel milliseconds, number of timed launches)."""
+    """(summed kernel milliseconds, number of kernel executions timed)."""
     total = ctypes.c_double()
     count = ctypes.c_int64()
     _check(library().hg_timing_end(plan.handle, ctypes.byref(total), ctypes.byref(count)))

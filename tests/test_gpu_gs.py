@@ -224,3 +224,27 @@ def test_consistent_target_fixed_point():
     phase, lev2, nm = run_gs(plan, t, phi_star, 5)
     assert np.array_equal(lev2, lv)
     assert nm.max() <= 1e-9
+
+
+def test_kernel_timing_modes_count_executions_and_leave_results_alone():
+    """hg_timing_begin/end: one repeat times each launch, R repeats time R
+    back-to-back executions per launch; after timing_end the plain call is
+    bitwise what it was before."""
+    h, w = 256, 256
+    t, phi = wl.target_and_phase(h, w, seed=10)
+    plan = make_plan(h, w, 8, True)
+    before = run_gs(plan, t, phi, 6)
+    for repeats in (1, 4):
+        hg.hg_timing_begin(plan, hg.HG_KERNEL_GS_REPLAY, repeats)
+        run_gs(plan, t, phi, 6)
+        ms, count = hg.hg_timing_end(plan)
+        assert count == 6 * repeats and ms > 0.0
+        hg.hg_timing_begin(plan, hg.HG_KERNEL_GS_SLM, repeats)
+        run_gs(plan, t, phi, 6)
+        ms, count = hg.hg_timing_end(plan)
+        assert count == 6 * repeats and ms > 0.0
+    after = run_gs(plan, t, phi, 6)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    with pytest.raises(RuntimeError):
+        hg.hg_timing_begin(plan, hg.HG_KERNEL_GS_SLM, 0)
