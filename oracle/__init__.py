@@ -25,6 +25,8 @@ step by step in the order the method performs it:
   gs.py           Gerchberg-Saxton error-reduction iteration (Gerchberg &
                   Saxton 1972; Fienup 1982).
   ospr.py         One-Step Phase-Retrieval (Cable, Buckley et al. 2004).
+  grad.py         gradient-descent hologram optimisation: multi-plane NMSE
+                  loss, its Wirtinger gradient and Adam (Kingma & Ba 2015).
 
 Readings taken where the paper is silent are listed in the design doc.  Every
 function is pinned by ``tests/test_oracle_*.py`` against closed forms,
@@ -37,10 +39,12 @@ from .constraints import (quantise_level, quantise_phase_level, phase_only,
 from .metrics import nmse
 from .gs import gs_iterate
 from .ospr import ospr
+from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
     "fresnel_chirp", "fresnel_geometry", "propagate",
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
     "binarise", "nmse", "gs_iterate", "ospr",
+    "source_chirp", "loss_and_gradient", "adam_update", "grad_descent",
 ]
