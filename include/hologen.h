@@ -139,6 +139,40 @@ hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illu
 hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_sub,
                   uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
 
+/* Gradient-descent hologram optimisation: the method added beyond the
+ * paper's library, whose further algorithms are left to future work (Sec. 8).
+ * The parameter is the continuous SLM phase phi; each of the n_planes replay
+ * planes j is given by its own plan (all of one width and height; HG_FOURIER
+ * or HG_FRESNEL at its own distance; modulation and levels are ignored):
+ *   V_j = Q1_j exp(i phi),  U_j = FFT2(V_j),  I_j = |U_j|^2
+ *   L   = sum_j NMSE(I_j, ifftshift(target_amp_j)^2)   (NMSE as in hg_gs_iterate,
+ *         sum I_j = (H W)^2 by Parseval)
+ *   dL/dphi = sum_j 2 Im(conj(V_j) F^H(dL/dI_j * U_j)),  F^H = H W IFFT2,
+ *   dL/dI_j = 2 (I_j/sum I_j - T_j/sum T_j) / (sum I_j sum (T_j/sum T_j)^2).
+ * V_j is recomputed from phi in the adjoint pass, never stored.
+ * planes     [n_planes] plans, 1 <= n_planes <= 16.                 (required)
+ * target_amp [n_planes][H][W] float, centred, >= 0, each not all zero.  (required)
+ * workspace  hg_grad_workspace_bytes(planes[0], n_planes) bytes.    (required)
+ * Invalid arguments return HG_ERR_INVALID_ARGUMENT before anything is enqueued. */
+size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes);
+
+/* One evaluation at phase [H][W] (read only): grad [H][W] float receives
+ * dL/dphi, loss [1] float receives L; either may be NULL (both NULL: no work). */
+hg_status hg_grad(const hg_plan* planes, int32_t n_planes, const float* target_amp, const float* phase,
+                  float* grad, float* loss, void* workspace, hipStream_t stream);
+
+/* `steps` Adam steps (Kingma & Ba 2015) on phase [H][W], in place:
+ *   g = dL/dphi; m = beta1 m + (1 - beta1) g; v = beta2 v + (1 - beta2) g^2;
+ *   phi -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * t = first_step, first_step + 1, ...  adam_m and adam_v [H][W] float hold the
+ * moments across calls (zero them before t = 1).  loss [steps + 1] float or
+ * NULL: loss[k] = L of the phase before step k + 1, loss[steps] = L of the
+ * returned phase.  steps >= 0, first_step >= 1, lr > 0, beta1 and beta2 in
+ * [0, 1), eps > 0. */
+hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* target_amp, float* phase,
+                       float* adam_m, float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1,
+                       float beta2, float eps, float* loss, void* workspace, hipStream_t stream);
+
 /* Diagnostics: per-kernel timing with HIP events.
  * hg_timing_begin makes every later launch of `kernel` made by calls on this
  * plan a timed launch on the call's stream, until hg_timing_end.

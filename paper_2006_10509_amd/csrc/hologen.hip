@@ -93,6 +93,8 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->col.gs_col, e->col.lds));
   chk(allow_lds(e->col.gs_col_nmse, e->col.lds));
   chk(allow_lds(e->col.ospr_b, e->col.lds));
+  chk(allow_lds(e->row.grad_row, e->row.lds));
+  chk(allow_lds(e->col.grad_col, e->col.lds));
   return err;
 }
 
@@ -299,6 +301,136 @@ void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const flo
   hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, w.stats, nb, n, illum ? 1 : 0,
                      intensity_sum, w.sc);
+}
+
+// Workspace of the gradient method for `planes` replay planes:
+// field | dL/dphi accumulator | Scalars per plane | stats | loss partials
+// [kNmseChunk states][planes][column workgroups] | tiled target per plane.
+struct GradLayout {
+  size_t acc, sc, stats, partials, target, target_stride, total;
+};
+
+GradLayout grad_layout(hg_plan p, int planes) {
+  const size_t n = npix(p);
+  GradLayout g{};
+  g.acc = align_up(n * sizeof(float2));
+  g.sc = g.acc + align_up(n * sizeof(float));
+  g.stats = g.sc + align_up((size_t)planes * sizeof(Scalars));
+  g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
+  g.target = g.partials + align_up((size_t)kNmseChunk * planes * p->col_blocks * sizeof(float));
+  g.target_stride = align_up((size_t)p->col_blocks * p->col->col.cols * p->desc.height * sizeof(float));
+  g.total = g.target + (size_t)planes * g.target_stride;
+  return g;
+}
+
+constexpr int kMaxPlanes = 16;
+
+hg_status validate_planes(const hg_plan* planes, int n_planes) {
+  if (!planes) return fail(HG_ERR_INVALID_ARGUMENT, "planes is NULL");
+  if (n_planes < 1 || n_planes > kMaxPlanes) return fail(HG_ERR_INVALID_ARGUMENT, "n_planes must be in 1..16");
+  for (int j = 0; j < n_planes; ++j) {
+    if (!planes[j]) return fail(HG_ERR_INVALID_ARGUMENT, "planes[" + std::to_string(j) + "] is NULL");
+    if (planes[j]->desc.width != planes[0]->desc.width || planes[j]->desc.height != planes[0]->desc.height)
+      return fail(HG_ERR_INVALID_ARGUMENT, "all planes must have the same width and height");
+  }
+  return HG_OK;
+}
+
+// One gradient evaluation per step for `steps` steps (Adam when m != null),
+// then, when final_loss, the loss of the state the last step leaves.
+// loss[k] receives the summed NMSE of state k (nullable).
+hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float* phase, float* grad, float* m,
+                   float* v, int steps, int first_step, float lr, float beta1, float beta2, float eps, float* loss,
+                   bool final_loss, void* workspace, hipStream_t stream) {
+  hg_plan p0 = planes[0];
+  const int W = p0->desc.width, H = p0->desc.height;
+  const size_t n = npix(p0);
+  const GradLayout L = grad_layout(p0, P);
+  char* ws = static_cast<char*>(workspace);
+  float2* field = reinterpret_cast<float2*>(ws);
+  float* acc = reinterpret_cast<float*>(ws + L.acc);
+  Scalars* sc = reinterpret_cast<Scalars*>(ws + L.sc);
+  double* stats = reinterpret_cast<double*>(ws + L.stats);
+  float* partials = reinterpret_cast<float*>(ws + L.partials);
+  const RowKernels& rk = p0->row->row;
+  const ColKernels& ck = p0->col->col;
+  const int cols = ck.cols;
+  const uint32_t tiled_n = (uint32_t)p0->col_blocks * cols * H;
+  const int nb = stats_blocks(n);
+  for (int j = 0; j < P; ++j) {
+    const float* tj = target_amp + (size_t)j * n;
+    float* tiled = reinterpret_cast<float*>(ws + L.target + (size_t)j * L.target_stride);
+    hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cols,
+                       tiled_n);
+    hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, (const float*)nullptr, n,
+                       stats);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
+                       (double)n * (double)n, sc + j);
+  }
+  GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
+  fa.field = field;
+  fa.phase0 = phase;
+  fa.H = H;
+  fa.tw = p0->tw_row[0];
+  fa.twr = p0->tw_row[1];
+  GsColArgs ca{};
+  ca.field = field;
+  ca.W = W;
+  ca.H = H;
+  ca.tw = p0->tw_col[0];
+  ca.twr = p0->tw_col[1];
+  GradRowArgs ga{};
+  ga.field = field;
+  ga.phase = phase;
+  ga.H = H;
+  ga.acc = acc;
+  ga.grad_out = grad;
+  ga.m = m;
+  ga.v = v;
+  ga.lr = lr;
+  ga.beta1 = beta1;
+  ga.beta2 = beta2;
+  ga.eps = eps;
+  ga.tw = p0->tw_row[0];
+  ga.twr = p0->tw_row[1];
+  const bool backward = grad || m;
+  auto plane_chirp = [&](int j, const float2*& qy, const float2*& qx) {
+    const bool fres = planes[j]->desc.propagation == HG_FRESNEL;
+    qy = fres ? planes[j]->q1y : nullptr;
+    qx = fres ? planes[j]->q1x : nullptr;
+  };
+  const int states = steps + (final_loss ? 1 : 0);
+  int chunk0 = 0;
+  for (int k = 0; k < states; ++k) {
+    const bool is_step = k < steps;
+    if (is_step && m) {
+      const int t = first_step + k;
+      ga.bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+      ga.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+    }
+    for (int j = 0; j < P; ++j) {
+      plane_chirp(j, fa.q1y, fa.q1x);
+      hipLaunchKernelGGL(rk.gs_start, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, fa);
+      ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
+      ca.sc = sc + j;
+      ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * p0->col_blocks : nullptr;
+      if (is_step && backward) {
+        hipLaunchKernelGGL(ck.grad_col, dim3(p0->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+        plane_chirp(j, ga.q1y, ga.q1x);
+        ga.first = j == 0;
+        ga.last = j == P - 1;
+        hipLaunchKernelGGL(rk.grad_row, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+      } else if (loss) {
+        hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p0->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+      }
+    }
+    if (loss && (k - chunk0 == kNmseChunk - 1 || k == states - 1)) {
+      hipLaunchKernelGGL(k_loss_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
+                         (const float*)partials, p0->col_blocks, P, (const Scalars*)sc, loss + chunk0);
+      chunk0 = k + 1;
+    }
+  }
+  return launch_status("gradient launch");
 }
 
 }  // namespace
@@ -553,6 +685,43 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, w.partials, p->row_blocks,
                        (const Scalars*)w.sc, nmse);
   return launch_status("hg_ospr launch");
+}
+
+size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes) {
+  if (!plan || n_planes < 1 || n_planes > kMaxPlanes) return 0;
+  return grad_layout(plan, n_planes).total;
+}
+
+hg_status hg_grad(const hg_plan* planes, int32_t n_planes, const float* target_amp, const float* phase, float* grad,
+                  float* loss, void* workspace, hipStream_t stream) {
+  hg_status st = validate_planes(planes, n_planes);
+  if (st != HG_OK) return st;
+  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (!grad && !loss) return HG_OK;
+  // one evaluation: the phase is only read (no Adam state)
+  return grad_run(planes, n_planes, target_amp, const_cast<float*>(phase), grad, nullptr, nullptr, grad ? 1 : 0,
+                  1, 0.f, 0.f, 0.f, 0.f, loss, grad == nullptr, workspace, stream);
+}
+
+hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* target_amp, float* phase, float* adam_m,
+                       float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1, float beta2, float eps,
+                       float* loss, void* workspace, hipStream_t stream) {
+  hg_status st = validate_planes(planes, n_planes);
+  if (st != HG_OK) return st;
+  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!phase || !adam_m || !adam_v) return fail(HG_ERR_INVALID_ARGUMENT, "phase/adam_m/adam_v is NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (steps < 0) return fail(HG_ERR_INVALID_ARGUMENT, "steps must be >= 0");
+  if (first_step < 1) return fail(HG_ERR_INVALID_ARGUMENT, "first_step must be >= 1");
+  if (!(std::isfinite(lr) && lr > 0.f)) return fail(HG_ERR_INVALID_ARGUMENT, "lr must be finite and > 0");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return fail(HG_ERR_INVALID_ARGUMENT, "beta1 and beta2 must be in [0, 1)");
+  if (!(std::isfinite(eps) && eps > 0.f)) return fail(HG_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
+  if (steps == 0 && !loss) return HG_OK;
+  return grad_run(planes, n_planes, target_amp, phase, nullptr, adam_m, adam_v, steps, first_step, lr, beta1, beta2,
+                  eps, loss, loss != nullptr, workspace, stream);
 }
 
 hg_status hg_timing_begin(hg_plan p, int32_t kernel, int32_t repeats) {

@@ -18,6 +18,11 @@
 //     k_ospr_c        row FFT -> |.|^2 accumulated (fftshift on store) [-> NMSE]
 //   Propagation (Fourier / single-FFT Fresnel):
 //     k_prop_row, k_prop_col
+//   Gradient-descent hologram (multi-plane NMSE loss, Wirtinger gradient, Adam):
+//     k_gs_row_start  phi -> Q1_j exp(i phi) -> row FFT    (continuous mode)
+//     k_gs_col        column FFT -> loss partial, dL/dconj(U) -> inverse column FFT
+//     k_grad_row      inverse row FFT -> 2 Im(conj(V_j) G_j) summed over planes
+//                     [-> gradient out] [-> Adam step on phi]
 //
 // Conventions.  The field is row-major [H][W] complex64 (float2).  The forward
 // transform uses exp(-2 pi i ...) and is unnormalised; inverse transforms
@@ -49,6 +54,7 @@ struct Scalars {
   float b;          // N_px / sum(T^2): normaliser of the target intensity
   double denom;     // N_px^2 sum(T^4) / sum(T^2)^2 = N_px^2 sum (T_I / sum T_I)^2
   double sum_t2, sum_t4, sum_a2;
+  float g;          // 2 a / denom: dNMSE/dI = g (a I - b T^2) for the gradient pass
 };
 
 // SLM constraint shared by the GS kernels.
@@ -547,9 +553,15 @@ struct GsColArgs {
   const float2* twr;
 };
 
-// Replay-plane pass: column FFT -> R_k; NMSE partial of |R_k|^2 against T^2;
-// REPLACE: R' = T R / |R| -> inverse column FFT -> field.
-template <int N, bool REPLACE>
+// Replay-plane pass of one state.  Column FFT -> R (the forward FFT2 of the
+// SLM field completes here); NMSE partial sum(d^2), d = a |R|^2 - b T^2; then
+//   COL_NMSE:    nothing more (last state of a call: no write-back);
+//   COL_REPLACE: R' = T R / |R| (Gerchberg-Saxton amplitude replacement);
+//   COL_GRAD:    R' = dL/dconj(R) = g d R (Wirtinger derivative of the NMSE);
+// -> inverse column FFT (unscaled: with the inverse row FFT of the next pass
+// it is the adjoint F^H of the forward FFT2) -> field.
+enum { COL_NMSE = 0, COL_REPLACE = 1, COL_GRAD = 2 };
+template <int N, int MODE>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   using C = ColCfg<N>;
   using P = typename C::P;
@@ -558,6 +570,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   using L1 = Layout<P, false, true>;
   using LB = Layout<P, true, true>;
   static_assert(LB::R == L0::R, "layout mismatch");
+  constexpr bool BACK = MODE != COL_NMSE;
   __shared__ float red[C::THREADS / 64];
   const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -571,34 +584,120 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   const uint32_t tbase = (uint32_t)tile * N * C::C + c;
   for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, tbase + (uint32_t)ky * C::C); });
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, true, REPLACE>;
+  using TW = PassTwiddles<P, C::THREADS, true, BACK>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if constexpr (TW::USES_LDS) __syncthreads();
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   float acc = 0.f;
   const bool nm = a.partials != nullptr;
-  const float sa = nm ? a.sc->a : 0.f;
-  const float sb = nm ? a.sc->b : 0.f;
+  const bool scaled = nm || MODE == COL_GRAD;
+  const float sa = scaled ? a.sc->a : 0.f;
+  const float sb = scaled ? a.sc->b : 0.f;
+  const float sg = MODE == COL_GRAD ? a.sc->g : 0.f;
   for_layout<L1>(t, [&](int s, int) {
     const float2 R = v[s];
     const float tv = tgt[s];
     const float I = cnorm(R);
     const float d = I * sa - tv * tv * sb;
     acc = fmaf(d, d, acc);
-    if constexpr (REPLACE) {
+    if constexpr (MODE == COL_REPLACE) {
       const float k = tv * rsqrtf(I);
       v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(tv, 0.0f);
+    } else if constexpr (MODE == COL_GRAD) {
+      const float k = sg * d;
+      v[s] = make_float2(R.x * k, R.y * k);
     }
   });
   if (nm) {
     const float s = block_sum<C::THREADS>(live ? acc : 0.0f, red);
     if (threadIdx.x == 0) a.partials[tile] = s;
   }
-  if constexpr (REPLACE) {
+  if constexpr (BACK) {
     tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
     if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, (uint32_t)y * a.W + x, v[s]); });
   }
+}
+
+// ===========================================================================
+// Gradient-descent hologram optimisation: adjoint row pass
+// ===========================================================================
+struct GradRowArgs {
+  const float2* field;     // output of the COL_GRAD pass of this plane
+  float* phase;            // SLM phase phi [H][W]; updated in place by the Adam step
+  int H;
+  const float2* q1y;       // source chirp of this plane; null -> Fourier plane
+  const float2* q1x;
+  float* acc;              // dL/dphi summed over the planes so far [H][W]
+  int first, last;         // first plane: no accumulator read; last: finish
+  float* grad_out;         // last plane: dL/dphi; may be null
+  float* m;                // last plane: Adam moments [H][W]; null -> no update
+  float* v;
+  float lr, beta1, beta2, eps;
+  float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
+  const float2* tw;
+  const float2* twr;
+};
+
+// Inverse row FFT (completes G = F^H dL/dconj(U) of this plane) -> V = Q1
+// exp(i phi) recomputed from phi rather than stored -> g = 2 Im(conj(V) G)
+// added to the sum over planes; after the last plane the sum is written out
+// and/or one Adam step updates phi.  The accumulator, moments and phase are
+// loaded with the field, before the transform.
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using LL = RowLds<N>;
+  using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
+  using LF = Layout<P, false, false>;  // its last stage
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  float ph[P::REGS], ac[P::REGS], mm[P::REGS], vv[P::REGS];
+  const bool adam = a.last && a.m != nullptr;
+  for_layout<LF>(t, [&](int s, int x) {
+    ph[s] = ldg(a.phase, row + x);
+    ac[s] = a.first ? 0.0f : ldg(a.acc, row + x);
+    mm[s] = adam ? ldg(a.m, row + x) : 0.0f;
+    vv[s] = adam ? ldg(a.v, row + x) : 0.0f;
+  });
+  issue_loads_here();
+  using TW = PassTwiddles<P, C::THREADS, false, true>;
+  using QX = RowTable<N, LF>;
+  TW tw;
+  QX qx;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  const bool fres = a.q1y != nullptr;
+  if (fres) qx.begin(a.q1x, t);
+  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+  const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
+  if (!rt.live) return;   // no barrier follows
+  for_layout<LF>(t, [&](int s, int x) {
+    const uint32_t i = row + x;
+    float sn, cs;
+    sincosf(ph[s], &sn, &cs);
+    float2 V = make_float2(cs, sn);
+    if (fres) V = cmul(V, cmul(qy, qx.at(s, x)));
+    const float2 G = v[s];
+    const float g = ac[s] + 2.0f * (V.x * G.y - V.y * G.x);
+    if (!a.last) {
+      stg(a.acc, i, g);
+      return;
+    }
+    if (a.grad_out) stg(a.grad_out, i, g);
+    if (adam) {
+      const float m1 = a.beta1 * mm[s] + (1.0f - a.beta1) * g;
+      const float v1 = a.beta2 * vv[s] + (1.0f - a.beta2) * g * g;
+      stg(a.m, i, m1);
+      stg(a.v, i, v1);
+      stg(a.phase, i, ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps));
+    }
+  });
 }
 
 // ===========================================================================
@@ -751,6 +850,7 @@ struct RowKernels {
   void (*gs_row_general)(GsRowArgs); // outputs / illumination / any mode
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
+  void (*grad_row)(GradRowArgs);
   int teams, threads;
   size_t lds;
 };
@@ -759,6 +859,7 @@ struct ColKernels {
   void (*prop_inv)(PropColArgs);
   void (*gs_col)(GsColArgs);
   void (*gs_col_nmse)(GsColArgs);
+  void (*grad_col)(GsColArgs);
   void (*ospr_b)(OsprColArgs);
   int cols, threads;
   size_t lds;
@@ -800,10 +901,12 @@ LengthEntry make_length_entry() {
   e.row.gs_row_general = k_gs_row<N, -1, false>;
   e.row.ospr_a = k_ospr_a<N>;
   e.row.ospr_c = k_ospr_c<N>;
+  e.row.grad_row = k_grad_row<N>;
   e.row.teams = RowCfg<N>::TEAMS;
   e.row.threads = RowCfg<N>::THREADS;
   e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
-  e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, true>, k_gs_col<N, false>, k_ospr_b<N>,
+  e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
+           k_gs_col<N, COL_GRAD>, k_ospr_b<N>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
   using PR = typename RowCfg<N>::P;
   using PC = typename ColCfg<N>::P;

@@ -103,6 +103,7 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __r
     sc->a = (float)(npx / s_i);
     sc->b = (float)(npx / t2);
     sc->denom = npx * npx * t4 / (t2 * t2);
+    sc->g = (float)(2.0 * (npx / s_i) / sc->denom);
   }
 }
 
@@ -116,6 +117,23 @@ __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce(const float* __re
   for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];
   s = block_sum_f64<STATS_THREADS>(s, red);
   if (threadIdx.x == 0) nmse[blockIdx.x] = (float)(s / sc->denom);
+}
+
+// loss[k] = sum_j (sum_wg partials[k][j][wg]) / denom_j: the summed NMSE of the
+// `planes` replay planes of state k, one workgroup per state, fixed order.
+__global__ __launch_bounds__(STATS_THREADS) void k_loss_reduce(const float* __restrict__ partials, int nwg,
+                                                               int planes, const Scalars* __restrict__ sc,
+                                                               float* __restrict__ loss) {
+  __shared__ double red[STATS_THREADS];
+  double total = 0.0;
+  for (int j = 0; j < planes; ++j) {
+    const float* p = partials + ((size_t)blockIdx.x * planes + j) * nwg;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];
+    s = block_sum_f64<STATS_THREADS>(s, red);
+    total += s / sc[j].denom;
+  }
+  if (threadIdx.x == 0) loss[blockIdx.x] = (float)total;
 }
 
 }  // namespace hg

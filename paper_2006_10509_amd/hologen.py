@@ -39,8 +39,8 @@ HG_KERNEL_PROP_ROW = 6
 HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
-            "hg_propagate", "hg_gs_iterate", "hg_ospr", "hg_timing_begin", "hg_timing_end",
-            "hg_error")
+            "hg_propagate", "hg_gs_iterate", "hg_ospr", "hg_grad_workspace_bytes", "hg_grad",
+            "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
 
 
 class hg_plan_desc(ctypes.Structure):
@@ -89,6 +89,14 @@ def library() -> ctypes.CDLL:
     lib.hg_gs_iterate.restype = i32
     lib.hg_ospr.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr.restype = i32
+    lib.hg_grad_workspace_bytes.argtypes = [vp, i32]
+    lib.hg_grad_workspace_bytes.restype = sz
+    lib.hg_grad.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp]
+    lib.hg_grad.restype = i32
+    f32 = ctypes.c_float
+    lib.hg_grad_adam.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, i32, i32, f32, f32, f32, f32,
+                                 vp, vp, vp]
+    lib.hg_grad_adam.restype = i32
     lib.hg_timing_begin.argtypes = [vp, i32, i32]
     lib.hg_timing_begin.restype = i32
     lib.hg_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -238,6 +246,95 @@ def hg_ospr(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=N
         _ptr(intensity, torch.float32, shape, "intensity"),
         _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
         _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+
+
+def _workspace(ws, need: int, name: str = "workspace") -> int:
+    import torch
+    ptr = _ptr(ws, torch.uint8, None, name)
+    if ws.numel() < need:
+        raise ValueError(f"{name} has {ws.numel()} bytes, the call needs {need}")
+    return ptr
+
+
+def _plans(planes):
+    planes = list(planes)
+    if not planes:
+        raise ValueError("at least one plane is required")
+    return planes, (ctypes.c_void_p * len(planes))(*[p.handle for p in planes])
+
+
+def grad_workspace_bytes(planes) -> int:
+    planes, _ = _plans(planes)
+    return int(library().hg_grad_workspace_bytes(planes[0].handle, len(planes)))
+
+
+def grad_workspace(planes, device="cuda"):
+    import torch
+    return torch.empty(grad_workspace_bytes(planes), dtype=torch.uint8, device=device)
+
+
+def hg_grad(planes, target_amp, phase, workspace, grad=None, loss=None, stream=None) -> None:
+    """Loss and/or dL/dphi of the multi-plane NMSE at ``phase`` (read only).
+    ``target_amp`` is [n_planes, H, W] (centred amplitudes), one per plan."""
+    import torch
+    planes, arr = _plans(planes)
+    shape = (planes[0].height, planes[0].width)
+    _check(library().hg_grad(
+        arr, len(planes), _ptr(target_amp, torch.float32, (len(planes),) + shape, "target_amp"),
+        _ptr(phase, torch.float32, shape, "phase"), _ptr(grad, torch.float32, shape, "grad", optional=True),
+        _ptr(loss, torch.float32, (1,), "loss", optional=True),
+        _workspace(workspace, grad_workspace_bytes(planes)), _stream(stream)))
+
+
+def hg_grad_adam(planes, target_amp, phase, adam_m, adam_v, steps: int, workspace, first_step: int = 1,
+                 lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8, loss=None, stream=None) -> None:
+    """``steps`` Adam steps on ``phase`` in place; ``loss`` [steps + 1] or None."""
+    import torch
+    planes, arr = _plans(planes)
+    shape = (planes[0].height, planes[0].width)
+    _check(library().hg_grad_adam(
+        arr, len(planes), _ptr(target_amp, torch.float32, (len(planes),) + shape, "target_amp"),
+        _ptr(phase, torch.float32, shape, "phase"), _ptr(adam_m, torch.float32, shape, "adam_m"),
+        _ptr(adam_v, torch.float32, shape, "adam_v"), int(steps), int(first_step), float(lr),
+        float(betas[0]), float(betas[1]), float(eps),
+        _ptr(loss, torch.float32, (int(steps) + 1,), "loss", optional=True),
+        _workspace(workspace, grad_workspace_bytes(planes)), _stream(stream)))
+
+
+_LOSS_FN = None
+
+
+def hologram_loss(phase, target_amp, planes, workspace=None):
+    """Differentiable multi-plane NMSE loss L(phase) as a 0-dim tensor.
+
+    A torch.autograd.Function over hg_grad: when ``phase`` requires a gradient
+    the forward call also runs the adjoint passes (the field is recomputed
+    from the phase inside them, never stored) and keeps only dL/dphase for
+    the backward call."""
+    global _LOSS_FN
+    import torch
+    if _LOSS_FN is None:
+        class _HologramLoss(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, phi, target, plane_list, ws):
+                loss = torch.empty(1, dtype=torch.float32, device=phi.device)
+                if ctx.needs_input_grad[0]:
+                    grad = torch.empty_like(phi)
+                    hg_grad(plane_list, target, phi.detach().contiguous(), ws, grad=grad, loss=loss)
+                    ctx.save_for_backward(grad)
+                else:
+                    hg_grad(plane_list, target, phi.detach().contiguous(), ws, loss=loss)
+                return loss[0]
+
+            @staticmethod
+            def backward(ctx, g):
+                (grad,) = ctx.saved_tensors
+                return g * grad, None, None, None
+
+        _LOSS_FN = _HologramLoss
+    if workspace is None:
+        workspace = grad_workspace(planes, device=phase.device)
+    return _LOSS_FN.apply(phase, target_amp, list(planes), workspace)
 
 
 def hg_timing_begin(plan: Plan, kernel: int, repeats: int = 1) -> None:

@@ -132,6 +132,29 @@ class OSPRWorkload:
         return np.stack([self.subframe_phase(n) for n in range(count)])
 
 
+@dataclass(frozen=True)
+class GradWorkload:
+    """Gradient-descent hologram problems: one continuous SLM phase per problem,
+    one synthetic target per (problem, plane); targets seeded 200 + 3 b + j,
+    starting phases 300 + b for problem b and plane j."""
+    name: str
+    height: int
+    width: int
+    distances: Tuple[float, ...]
+    steps: int
+    lr: float
+    problems: int
+    wavelength: float = WAVELENGTH_532NM
+    pitch: float = PITCH_8UM
+
+    def targets(self, b: int = 0) -> np.ndarray:
+        return np.stack([target_amplitude(self.height, self.width, 200 + 3 * b + j)
+                         for j in range(len(self.distances))])
+
+    def phase0(self, b: int = 0) -> np.ndarray:
+        return uniform_phase(self.height, self.width, 300 + b)
+
+
 # GS Fourier, 256x256, continuous phase, 20 iterations; target seed 0, phase seed 1.
 GS_FOURIER_256 = GSWorkload("gs_fourier_256x256_cont_20it", 256, 256, 20, 0, False, 0, 1)
 # GS Fresnel, 1024x1024, 8 levels, 100 iterations; lambda 532 nm, 8 um, z 0.5 m;
@@ -139,6 +162,13 @@ GS_FOURIER_256 = GSWorkload("gs_fourier_256x256_cont_20it", 256, 256, 20, 0, Fal
 GS_FRESNEL_1024 = GSWorkload("gs_fresnel_1024x1024_L8_100it", 1024, 1024, 100, 8, True, 2, 3)
 # OSPR binary phase, 2048x2048, 24 subframes; target seed 4, subframe seeds 10..33.
 OSPR_2048 = OSPRWorkload("ospr_2048x2048_24sub", 2048, 2048, 24, 4, 10)
+# Gradient-descent CGH, 1024x1024 phase, Fresnel planes at 0.40 / 0.45 / 0.50 m
+# (532 nm, 8 um), summed NMSE loss, Adam lr 0.05, 500 steps, 8 problems.
+GRAD_3PLANE_1024 = GradWorkload("grad_fresnel3_1024x1024_adam500", 1024, 1024, (0.40, 0.45, 0.50), 500, 0.05, 8)
+# Time-to-NMSE comparison: the 1024x1024 Fresnel geometry of GS_FRESNEL_1024
+# (target seed 2, phase seed 3, z 0.5 m) with a continuous phase; the threshold
+# is the NMSE continuous GS reaches after 100 iterations.
+GS_FRESNEL_1024_CONT = GSWorkload("gs_fresnel_1024x1024_cont_100it", 1024, 1024, 100, 0, True, 2, 3)
 
 
 def batched_mix() -> List[Tuple[int, int, int]]:

@@ -1,0 +1,168 @@
+"""GPU parity of the gradient-descent hologram path (hg_grad, hg_grad_adam and
+the autograd wrapper) against the FP64 oracle (oracle/grad.py), same FP32
+inputs.
+
+Bars.  Loss: within 1e-4 relative (the NMSE bar).  Gradient: relative L2 of
+at most 1e-4 against the oracle's gradient; the GPU path computes it with
+four FP32 transforms (FFT2 then the adjoint FFT2), each within 1e-5 relative
+L2, plus pointwise products, so 1e-4 leaves a tenfold margin.  Adam
+trajectories: loss curves within 1e-3 relative over the first 50 steps
+(FP32 moments against FP64 ones drift slowly; beyond that only the final
+loss is compared, parity unpinned by any closed form)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_10509_amd import hologen as hg
+from paper_2006_10509_amd import workloads as wl
+from gpu_util import dev, host, rel_l2, torch_mod
+
+pytestmark = pytest.mark.gpu
+WAVE, PITCH = 532e-9, 8e-6
+
+
+def make_planes(h, w, distances):
+    """distance None -> Fourier plane."""
+    planes, dicts = [], []
+    for z in distances:
+        if z is None:
+            planes.append(hg.Plan(w, h, hg.HG_FOURIER))
+            dicts.append(None)
+        else:
+            planes.append(hg.Plan(w, h, hg.HG_FRESNEL, WAVE, PITCH, z))
+            dicts.append(dict(wavelength=WAVE, pitch=PITCH, distance=z))
+    return planes, dicts
+
+
+def problem(h, w, n_planes, seed):
+    rng = np.random.default_rng(seed)
+    targets = np.stack([wl.target_amplitude(h, w, seed + 10 + j) for j in range(n_planes)])
+    phi = rng.uniform(0, 2 * np.pi, (h, w)).astype(np.float32)
+    return targets, phi
+
+
+def gpu_loss_grad(planes, targets, phi):
+    torch = torch_mod()
+    g = torch.empty(phi.shape, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    hg.hg_grad(planes, dev(targets), dev(phi), hg.grad_workspace(planes), grad=g, loss=loss)
+    return float(host(loss)[0]), host(g)
+
+
+@pytest.mark.parametrize("h,w,distances", [
+    (64, 64, [0.40, 0.45, 0.50]),
+    (90, 120, [None]),
+    (256, 256, [0.5]),
+    (120, 90, [0.45, None]),
+    (512, 1024, [0.5, 0.4]),
+    (1024, 1024, [0.40, 0.45, 0.50]),
+])
+def test_loss_and_gradient_match_oracle(h, w, distances):
+    print(f"grad {h}x{w} planes={distances}", flush=True)
+    planes, dicts = make_planes(h, w, distances)
+    targets, phi = problem(h, w, len(distances), h + w)
+    loss, g = gpu_loss_grad(planes, targets, phi)
+    ref_loss, ref_g, _ = oracle.loss_and_gradient(phi.astype(np.float64), list(targets.astype(np.float64)), dicts)
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss, (loss, ref_loss)
+    assert rel_l2(g, ref_g) <= 1e-4, rel_l2(g, ref_g)
+    # global-phase invariance holds at any size
+    assert abs(g.astype(np.float64).sum()) <= 1e-4 * np.abs(g).sum()
+
+
+def test_loss_only_call_matches_the_gradient_call():
+    torch = torch_mod()
+    planes, _ = make_planes(128, 128, [0.5, 0.4])
+    targets, phi = problem(128, 128, 2, 3)
+    loss_a, _ = gpu_loss_grad(planes, targets, phi)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    hg.hg_grad(planes, dev(targets), dev(phi), hg.grad_workspace(planes), loss=loss)
+    assert float(host(loss)[0]) == loss_a
+
+
+def test_consistent_target_gives_zero_loss_and_gradient():
+    h, w = 128, 120
+    planes, dicts = make_planes(h, w, [0.5])
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0, 2 * np.pi, (h, w))
+    q1 = oracle.source_chirp(h, w, dicts[0])
+    t = np.fft.fftshift(np.abs(np.fft.fft2(q1 * np.exp(1j * phi))))[None].astype(np.float32)
+    loss, g = gpu_loss_grad(planes, t, phi.astype(np.float32))
+    _, g_random = gpu_loss_grad(planes, problem(h, w, 1, 8)[0], phi.astype(np.float32))
+    assert loss <= 1e-9
+    assert np.abs(g).max() <= 1e-4 * np.abs(g_random).max()
+
+
+def run_adam(planes, targets, phi, steps, first=1, m=None, v=None, lr=0.05):
+    torch = torch_mod()
+    ph = dev(phi.copy())
+    mm = dev(np.zeros_like(phi)) if m is None else m
+    vv = dev(np.zeros_like(phi)) if v is None else v
+    loss = torch.empty(steps + 1, dtype=torch.float32, device="cuda")
+    hg.hg_grad_adam(planes, dev(targets), ph, mm, vv, steps, hg.grad_workspace(planes), first_step=first,
+                    lr=lr, loss=loss)
+    return ph, mm, vv, host(loss)
+
+
+@pytest.mark.parametrize("h,w,distances", [(64, 64, [0.40, 0.45, 0.50]), (256, 256, [0.5])])
+def test_adam_trajectory_matches_oracle(h, w, distances):
+    print(f"adam {h}x{w} planes={distances}", flush=True)
+    planes, dicts = make_planes(h, w, distances)
+    targets, phi = problem(h, w, len(distances), 7 * h)
+    steps = 50
+    ph, _, _, loss = run_adam(planes, targets, phi, steps)
+    ref = oracle.grad_descent(phi.astype(np.float64), list(targets.astype(np.float64)), dicts, steps, lr=0.05)
+    rel = np.abs(loss - np.array(ref["loss"])) / np.array(ref["loss"])
+    assert rel.max() <= 1e-3, (rel.max(), int(rel.argmax()))
+    assert loss[-1] < 0.5 * loss[0]
+
+
+def test_adam_resumes_bitwise_across_calls():
+    planes, _ = make_planes(128, 128, [0.5, 0.45])
+    targets, phi = problem(128, 128, 2, 21)
+    full_ph, full_m, full_v, full_loss = run_adam(planes, targets, phi, 20)
+    ph1, m1, v1, loss1 = run_adam(planes, targets, phi, 10)
+    ph2, m2, v2, loss2 = run_adam(planes, targets, host(ph1), 10, first=11, m=m1, v=v1)
+    assert np.array_equal(host(full_ph), host(ph2))
+    assert np.array_equal(host(full_m), host(m2)) and np.array_equal(host(full_v), host(v2))
+    assert np.array_equal(full_loss[:11], loss1) and np.array_equal(full_loss[10:], loss2)
+
+
+def test_autograd_wrapper_matches_hg_grad_and_drives_torch_adam():
+    torch = torch_mod()
+    h, w = 128, 128
+    planes, _ = make_planes(h, w, [0.5, 0.4])
+    targets, phi = problem(h, w, 2, 13)
+    ref_loss, ref_g = gpu_loss_grad(planes, targets, phi)
+    t = dev(targets)
+    p = dev(phi.copy()).requires_grad_(True)
+    loss = hg.hologram_loss(p, t, planes)
+    loss.backward()
+    assert float(loss.detach()) == ref_loss
+    assert np.array_equal(host(p.grad), ref_g)
+    # torch.optim.Adam over the wrapper follows the fused hg_grad_adam loop
+    opt = torch.optim.Adam([p], lr=0.05)
+    p.data.copy_(dev(phi))
+    ws = hg.grad_workspace(planes)
+    for _ in range(10):
+        opt.zero_grad()
+        hg.hologram_loss(p, t, planes, ws).backward()
+        opt.step()
+    _, _, _, fused = run_adam(planes, targets, phi, 10)
+    with torch.no_grad():
+        final = float(hg.hologram_loss(p, t, planes, ws))
+    assert abs(final - fused[-1]) <= 1e-4 * fused[-1]
+
+
+def test_argument_validation():
+    torch = torch_mod()
+    planes, _ = make_planes(64, 64, [0.5])
+    other = hg.Plan(32, 64, hg.HG_FOURIER)
+    targets, phi = problem(64, 64, 1, 1)
+    ws = hg.grad_workspace(planes)
+    with pytest.raises(RuntimeError):
+        hg.hg_grad(planes + [other], dev(np.concatenate([targets, targets])), dev(phi),
+                   hg.grad_workspace(planes + planes), loss=torch.empty(1, device="cuda"))
+    with pytest.raises(RuntimeError):
+        run_adam(planes, targets, phi, 3, first=0)
+    with pytest.raises(ValueError):
+        hg.hg_grad(planes, dev(targets), dev(phi), ws[:16], loss=torch.empty(1, device="cuda"))
