@@ -78,6 +78,88 @@ def cpu_baseline(workload, target, phi0, sample_iters: int):
                       f"including its one extra NMSE transform ({dt:.1f} s)"}
 
 
+def time_to_nmse(hg, wl, torch, stream) -> dict:
+    """Wall-clock time for gradient-descent CGH (Adam, lr 0.05, one Fresnel
+    plane, continuous phase) to reach the NMSE that continuous GS reaches after
+    100 iterations, on the same 1024x1024 target, starting phase and geometry;
+    both timed with HIP events on the launch stream, inputs resident."""
+    w = wl.GS_FRESNEL_1024_CONT
+    target, phi0 = w.inputs()
+    t = torch.from_numpy(target).cuda()
+    plan = hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, w.distance, hg.HG_PHASE, 0)
+    ws = plan.workspace()
+    nm = torch.empty(w.iterations + 1, dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run_gs():
+        ph = torch.from_numpy(phi0.copy()).cuda()
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_gs_iterate(plan, t, ph, w.iterations, ws, nmse=nm, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    run_gs()
+    gs_ms = run_gs()
+    threshold = float(nm[-1].item())
+    planes = [plan]
+    gws = hg.grad_workspace(planes)
+    tt = t[None].contiguous()
+    max_steps = 500
+
+    def run_grad(steps):
+        ph = torch.from_numpy(phi0.copy()).cuda()
+        m = torch.zeros_like(ph)
+        v = torch.zeros_like(ph)
+        loss = torch.empty(steps + 1, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_grad_adam(planes, tt, ph, m, v, steps, gws, lr=0.05, loss=loss, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b), loss.cpu().numpy()
+
+    run_grad(10)
+    full_ms, losses = run_grad(max_steps)
+    hit = [k for k, x in enumerate(losses) if x <= threshold]
+    steps = hit[0] if hit else None
+    grad_ms = run_grad(steps)[0] if steps else None
+    return {"workload": w.name, "threshold_nmse": threshold, "gs_iterations": w.iterations,
+            "gs_ms": round(gs_ms, 3), "grad_steps_to_threshold": steps,
+            "grad_ms_to_threshold": None if grad_ms is None else round(grad_ms, 3),
+            "grad_ms_per_step": round(full_ms / max_steps, 4), "grad_nmse_after_500": float(losses[-1]),
+            "optimizer": "adam lr 0.05, one Fresnel plane z 0.5 m, continuous phase"}
+
+
+def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
+    """The 3-plane gradient workload: `problems` problems of 500 Adam steps each
+    (one hg_grad_adam call per problem), problem-steps/s."""
+    w = wl.GRAD_3PLANE_1024
+    planes = [hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, z, hg.HG_PHASE, 0)
+              for z in w.distances]
+    gws = hg.grad_workspace(planes)
+    data = [(torch.from_numpy(w.targets(bi)).cuda(), torch.from_numpy(w.phase0(bi)).cuda())
+            for bi in range(problems)]
+    losses = torch.empty((problems, w.steps + 1), dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for bi, (tg, p0) in enumerate(data):
+        ph = p0.clone()
+        m = torch.zeros_like(ph)
+        v = torch.zeros_like(ph)
+        hg.hg_grad_adam(planes, tg, ph, m, v, w.steps, gws, lr=w.lr, loss=losses[bi], stream=stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    fin = losses[:, -1].cpu().numpy()
+    return {"workload": w.name, "problems": problems, "steps": w.steps, "planes": len(w.distances),
+            "ms": round(ms, 2), "problem_steps_per_s": round(problems * w.steps / (ms * 1e-3), 1),
+            "ms_per_step": round(ms / (problems * w.steps), 4),
+            "final_loss_mean": float(fin.mean()), "initial_loss_mean": float(losses[:, 0].mean().item())}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +167,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient-CGH measurements")
+    ap.add_argument("--grad-problems", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -165,6 +249,15 @@ def main() -> int:
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "iteration_gbs": round(iter_gbs, 1), "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)}
 
+    ttn = gb = None
+    if not args.no_grad:
+        log("time to NMSE: continuous GS vs gradient CGH")
+        ttn = time_to_nmse(hg, wl, torch, stream)
+        log(f"  {ttn}")
+        log(f"gradient CGH: {args.grad_problems} problems x 500 steps, 3 Fresnel planes")
+        gb = grad_batch(hg, wl, torch, stream, args.grad_problems)
+        log(f"  {gb}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_sample_iters} iterations")
@@ -178,7 +271,7 @@ def main() -> int:
                       "iterations_per_step": w.iterations, "levels": w.levels, "propagation": "fresnel",
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
                       "target_seed": w.target_seed, "phase_seed": w.phase_seed},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb}
     print(json.dumps(out), flush=True)
     return 0
 
