@@ -160,6 +160,99 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
             "final_loss_mean": float(fin.mean()), "initial_loss_mean": float(losses[:, 0].mean().item())}
 
 
+def _mix_inputs(item):
+    from paper_2006_10509_amd import workloads as wl
+    h, w, seed = item
+    return wl.target_and_phase(h, w, seed)
+
+
+def mix_inputs(wl):
+    """Inputs of the mixed batch, generated in worker processes.  Called before
+    this process touches the GPU, so the workers start from a GPU-free state."""
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(_mix_inputs, wl.batched_mix()))
+
+
+def batched_mix(hg, wl, torch, stream, inputs, iterations: int = 50) -> dict:
+    """The 64-hologram mixed batch (16 x 512^2, 24 x 1024^2, 16 x 2048^2,
+    8 x 1080x1920; Fourier GS, 4 levels, 50 iterations, NMSE of every state):
+    one hg_gs_iterate_batched call per shape against 64 hg_gs_iterate calls,
+    both on one stream with inputs resident, holograms/s."""
+    items = wl.batched_mix()
+    shapes = sorted({(h, w) for h, w, _ in items})
+    plans = {sh: hg.Plan(sh[1], sh[0], hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_PHASE_QUANTISED, 4) for sh in shapes}
+    groups = {sh: [i for i, (h, w, _) in enumerate(items) if (h, w) == sh] for sh in shapes}
+    targets = [torch.from_numpy(t).cuda() for t, _ in inputs]
+    phase0 = [torch.from_numpy(p).cuda() for _, p in inputs]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    single_ws = {sh: plans[sh].workspace() for sh in shapes}
+    seq_phase = [p.clone() for p in phase0]
+    seq_nmse = [torch.empty(iterations + 1, dtype=torch.float32, device="cuda") for _ in items]
+
+    def run_sequential():
+        for i, (h, w, _) in enumerate(items):
+            seq_phase[i].copy_(phase0[i])
+        torch.cuda.synchronize()
+        a.record(stream)
+        for i, (h, w, _) in enumerate(items):
+            hg.hg_gs_iterate(plans[(h, w)], targets[i], seq_phase[i], iterations, single_ws[(h, w)],
+                             nmse=seq_nmse[i], stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    bt = {sh: torch.stack([targets[i] for i in groups[sh]]) for sh in shapes}
+    bp0 = {sh: torch.stack([phase0[i] for i in groups[sh]]) for sh in shapes}
+    bp = {sh: bp0[sh].clone() for sh in shapes}
+    bn = {sh: torch.empty((len(groups[sh]), iterations + 1), dtype=torch.float32, device="cuda") for sh in shapes}
+    bws = {sh: torch.empty(hg.workspace_bytes_batched(plans[sh], len(groups[sh])), dtype=torch.uint8,
+                           device="cuda") for sh in shapes}
+
+    def run_batched():
+        for sh in shapes:
+            bp[sh].copy_(bp0[sh])
+        torch.cuda.synchronize()
+        a.record(stream)
+        for sh in shapes:
+            hg.hg_gs_iterate_batched(plans[sh], bt[sh], bp[sh], iterations, bws[sh], nmse=bn[sh], stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    run_sequential()
+    run_batched()
+    seq_ms = min(run_sequential() for _ in range(3))
+    bat_ms = min(run_batched() for _ in range(3))
+    same = all(torch.equal(bp[sh][k], seq_phase[i]) and torch.equal(bn[sh][k], seq_nmse[i])
+               for sh in shapes for k, i in enumerate(groups[sh]))
+    n = len(items)
+    return {"workload": "gs_fourier_L4_50it_mixed64", "holograms": n, "iterations": iterations,
+            "sequential_ms": round(seq_ms, 2), "batched_ms": round(bat_ms, 2),
+            "sequential_holograms_per_s": round(n / (seq_ms * 1e-3), 1),
+            "batched_holograms_per_s": round(n / (bat_ms * 1e-3), 1),
+            "speedup": round(seq_ms / bat_ms, 3), "identical_results": bool(same),
+            "launches": f"{len(shapes)} batched calls vs {n} single calls"}
+
+
+def rocfft_reference(torch, stream, n: int = 1024, reps: int = 200) -> dict:
+    """torch.fft (rocFFT) forward + inverse 2D transform of one n x n complex64
+    field, back to back: a vendor-library reference point, not part of the path."""
+    x = torch.randn((n, n), dtype=torch.complex64, device="cuda")
+    for _ in range(5):
+        x = torch.fft.ifft2(torch.fft.fft2(x))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        x = torch.fft.ifft2(torch.fft.fft2(x))
+    b.record(stream)
+    b.synchronize()
+    return {"what": f"torch.fft.fft2 + ifft2 of a {n}x{n} complex64 field (rocFFT)",
+            "us_per_pair": round(a.elapsed_time(b) / reps * 1e3, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +262,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-CGH measurements")
     ap.add_argument("--grad-problems", type=int, default=8)
+    ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -182,6 +276,10 @@ def main() -> int:
     from paper_2006_10509_amd import hologen as hg
     from paper_2006_10509_amd import workloads as wl
 
+    mixed = None
+    if not (args.no_batched or args.calibrate_copy):
+        log("generating the mixed-batch inputs")
+        mixed = mix_inputs(wl)
     if not torch.cuda.is_available():
         log("bench.py needs a GPU")
         return 1
@@ -258,6 +356,15 @@ def main() -> int:
         gb = grad_batch(hg, wl, torch, stream, args.grad_problems)
         log(f"  {gb}")
 
+    mix = None
+    if not args.no_batched:
+        log("mixed batch: 64 holograms, batched vs sequential")
+        mix = batched_mix(hg, wl, torch, stream, mixed)
+        log(f"  {mix}")
+
+    rf = rocfft_reference(torch, stream)
+    log(f"rocFFT reference: {rf}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_sample_iters} iterations")
@@ -271,7 +378,8 @@ def main() -> int:
                       "iterations_per_step": w.iterations, "levels": w.levels, "propagation": "fresnel",
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
                       "target_seed": w.target_seed, "phase_seed": w.phase_seed},
-           "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb}
+           "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
+           "batched_mix": mix, "rocfft_reference": rf}
     print(json.dumps(out), flush=True)
     return 0
 

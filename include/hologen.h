@@ -127,6 +127,20 @@ hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illu
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
                         hipStream_t stream);
 
+/* Gerchberg-Saxton on a batch of same-shape holograms in one launch per pass:
+ * exactly hg_gs_iterate applied to each item b < batch (bitwise the same
+ * results), with every pass launched once over all items, so that many small
+ * holograms fill the GPU together.  Holograms of several shapes run as one
+ * call per shape on one stream.  Item b uses target_amp + b H W,
+ * phase + b H W, levels + b H W and nmse + b (iterations + 1); the
+ * illumination (or NULL) is shared.  1 <= batch <= 65535 and
+ * batch H W < 2^32.  workspace: hg_workspace_bytes_batched(plan, batch)
+ * bytes (the fields of all items are resident together). */
+size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch);
+hg_status hg_gs_iterate_batched(hg_plan plan, int32_t batch, const float* target_amp, const float* illumination,
+                                float* phase, uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                                hipStream_t stream);
+
 /* One-Step Phase-Retrieval, binary phase (Sec. 7.3, HoloGenAlgOSPRCuda), on a
  * HG_FOURIER plan:
  *   for n < n_sub: G_n = IFFT2(ifftshift(target_amp exp(i sub_phase[n])));

@@ -153,7 +153,7 @@ struct hg_plan_s {
   float2* lvl_tab = nullptr;
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
   int row_blocks = 0, col_blocks = 0;
-  size_t off_scalars = 0, off_stats = 0, off_partials = 0, off_target = 0, ws_bytes = 0;
+  size_t ws_bytes = 0;     // workspace of one hologram (ws_layout(p, 1).total)
   std::vector<void*> allocations;
   // diagnostics: event pairs around launches of one kernel kind
   int timed_kernel = 0;
@@ -193,9 +193,9 @@ void free_plan(hg_plan p) {
 // the dispatch itself; with R > 1 repeats the kernel is launched R times back
 // to back between two hipEventRecord calls (see hg_timing_begin).
 template <class A>
-void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, int threads, size_t lds, A& args) {
+void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), dim3 blocks, int threads, size_t lds, A& args) {
   if (p->timed_kernel != kind || p->ev_error != hipSuccess) {
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+    hipLaunchKernelGGL(kernel, blocks, dim3(threads), lds, s, args);
     return;
   }
   if (p->ev_used == p->ev_start.size()) {
@@ -205,7 +205,7 @@ void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, i
     if (e != hipSuccess) {
       if (a) (void)hipEventDestroy(a);
       p->ev_error = e;
-      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+      hipLaunchKernelGGL(kernel, blocks, dim3(threads), lds, s, args);
       return;
     }
     p->ev_start.push_back(a);
@@ -215,11 +215,11 @@ void launch(hg_plan p, int kind, hipStream_t s, void (*kernel)(A), int blocks, i
   hipError_t e = hipSuccess;
   if (p->timed_repeats == 1) {
     void* argv[] = {&args};
-    e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(blocks), dim3(threads), argv, lds, s, a, b, 0);
+    e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), blocks, dim3(threads), argv, lds, s, a, b, 0);
   } else {
     e = hipEventRecord(a, s);
     for (int r = 0; e == hipSuccess && r < p->timed_repeats; ++r) {
-      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, args);
+      hipLaunchKernelGGL(kernel, blocks, dim3(threads), lds, s, args);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(b, s);
@@ -270,6 +270,28 @@ hg_status launch_status(const char* what) {
   return HG_OK;
 }
 
+// Workspace of `batch` same-shape holograms: fields [batch][H][W] complex64 |
+// Scalars [batch] | stats | NMSE partials [batch][kNmseChunk][workgroups] |
+// tiled targets [batch][tiles][H][C].  batch = 1 is the single-call layout.
+struct WsLayout {
+  size_t sc, stats, partials, target, total;
+  size_t partial_stride, target_stride;   // floats per batch item
+};
+
+WsLayout ws_layout(hg_plan p, int batch) {
+  const size_t n = (size_t)p->desc.width * (size_t)p->desc.height;
+  const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
+  WsLayout L{};
+  L.partial_stride = (size_t)kNmseChunk * nwg;
+  L.target_stride = (size_t)p->col_blocks * p->col->col.cols * p->desc.height;
+  L.sc = align_up((size_t)batch * n * sizeof(float2));
+  L.stats = L.sc + align_up((size_t)batch * sizeof(Scalars));
+  L.partials = L.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
+  L.target = L.partials + align_up((size_t)batch * L.partial_stride * sizeof(float));
+  L.total = L.target + align_up((size_t)batch * L.target_stride * sizeof(float));
+  return L;
+}
+
 struct Workspace {
   float2* field;
   Scalars* sc;
@@ -278,11 +300,12 @@ struct Workspace {
   float* target;   // target amplitude tiled for the column pass (k_tile_target)
 };
 
-Workspace carve(hg_plan p, void* ws) {
+Workspace carve(hg_plan p, void* ws, int batch = 1) {
+  const WsLayout L = ws_layout(p, batch);
   char* b = static_cast<char*>(ws);
-  return {reinterpret_cast<float2*>(b), reinterpret_cast<Scalars*>(b + p->off_scalars),
-          reinterpret_cast<double*>(b + p->off_stats), reinterpret_cast<float*>(b + p->off_partials),
-          reinterpret_cast<float*>(b + p->off_target)};
+  return {reinterpret_cast<float2*>(b), reinterpret_cast<Scalars*>(b + L.sc),
+          reinterpret_cast<double*>(b + L.stats), reinterpret_cast<float*>(b + L.partials),
+          reinterpret_cast<float*>(b + L.target)};
 }
 
 size_t npix(hg_plan p) { return (size_t)p->desc.width * (size_t)p->desc.height; }
@@ -295,12 +318,12 @@ int stats_blocks(size_t n) {
 }
 
 void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const float* illum, double intensity_sum,
-                   hipStream_t s) {
+                   Scalars* out, hipStream_t s) {
   const size_t n = npix(p);
   const int nb = stats_blocks(n);
   hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats);
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, w.stats, nb, n, illum ? 1 : 0,
-                     intensity_sum, w.sc);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, (const double*)w.stats, nb, n, illum ? 1 : 0,
+                     intensity_sum, out);
 }
 
 // Workspace of the gradient method for `planes` replay planes:
@@ -433,6 +456,102 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
   return launch_status("gradient launch");
 }
 
+// Gerchberg-Saxton on `batch` same-shape holograms stacked along the slowest
+// axis (batch = 1: one hologram).  Every pass is one launch over all items
+// (grid.y = batch item), so a batch of small holograms fills the GPU.
+hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* illumination, float* phase,
+                 uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
+  const int W = p->desc.width, H = p->desc.height;
+  const size_t n = npix(p);
+  const WsLayout L = ws_layout(p, batch);
+  Workspace w = carve(p, workspace, batch);
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+
+  GsRowArgs ra{};
+  ra.field = w.field;
+  ra.illum = illumination;
+  ra.H = H;
+  ra.px = (uint32_t)n;
+  if (p->desc.propagation == HG_FRESNEL) {
+    ra.q1y = p->q1y;
+    ra.q1x = p->q1x;
+  }
+  ra.slm.lvl_tab = p->lvl_tab;
+  ra.slm.levels = p->levels;
+  ra.slm.inv_delta = p->levels ? (float)((double)p->levels / (2.0 * M_PI)) : 0.0f;
+  ra.slm.inv_delta_f64 = p->levels ? (double)p->levels / (2.0 * M_PI) : 0.0;
+  ra.slm.half_step = p->levels ? make_float2((float)std::cos(M_PI / p->levels), (float)std::sin(M_PI / p->levels))
+                               : make_float2(1.0f, 0.0f);
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
+
+  const int cols = ck.cols;
+  const uint32_t tiled_n = (uint32_t)L.target_stride;
+  for (int b = 0; b < batch; ++b)
+    hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, target_amp + (size_t)b * n,
+                       w.target + (size_t)b * L.target_stride, H, W, cols, tiled_n);
+
+  GsColArgs ca{};
+  ca.field = w.field;
+  ca.W = W;
+  ca.H = H;
+  ca.target = w.target;
+  ca.sc = w.sc;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
+  ca.px = (uint32_t)n;
+  ca.target_stride = (uint32_t)L.target_stride;
+  ca.partial_stride = (uint32_t)L.partial_stride;
+
+  const int mode = p->levels == 0 ? GS_CONT
+                 : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
+  // steady-state kernel unless the pass needs illumination or produces outputs
+  void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
+
+  if (nmse)
+    for (int b = 0; b < batch; ++b) enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream);
+
+  const dim3 rows(p->row_blocks, batch), tiles(p->col_blocks, batch);
+  ra.phase0 = phase;
+  ra.phase_out = iterations == 0 ? phase : nullptr;
+  ra.levels_out = iterations == 0 ? levels : nullptr;
+  hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, ra);
+
+  int chunk0 = 0;  // first state of the pending reduction chunk
+  for (int k = 0; k <= iterations; ++k) {
+    const bool last = k == iterations;
+    if (last && !nmse) break;
+    ca.partials = nmse ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
+    if (last) {
+      hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
+    } else {
+      launch(p, HG_KERNEL_GS_REPLAY, stream, ck.gs_col, tiles, ck.threads, ck.lds, ca);
+    }
+    if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
+      hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
+                         (const float*)w.partials, p->col_blocks, (const Scalars*)w.sc, nmse + chunk0,
+                         L.partial_stride, (size_t)iterations + 1);
+      chunk0 = k + 1;
+    }
+    if (last) break;
+    ra.phase_out = k == iterations - 1 ? phase : nullptr;
+    ra.levels_out = k == iterations - 1 ? levels : nullptr;
+    void (*gs_row)(GsRowArgs) = (illumination || ra.phase_out) ? rk.gs_row_general : gs_row_hot;
+    launch(p, HG_KERNEL_GS_SLM, stream, gs_row, rows, rk.threads, rk.lds, ra);
+  }
+  return launch_status("hg_gs_iterate launch");
+}
+
+hg_status gs_validate(hg_plan p, const float* target_amp, const float* phase, int32_t iterations, void* workspace) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (iterations < 0) return fail(HG_ERR_INVALID_ARGUMENT, "iterations must be >= 0");
+  return HG_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -506,12 +625,7 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
   p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
   const size_t n = (size_t)W * H;
-  p->off_scalars = align_up(n * sizeof(float2));
-  p->off_stats = p->off_scalars + align_up(sizeof(Scalars));
-  p->off_partials = p->off_stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
-  const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
-  p->off_target = p->off_partials + align_up((size_t)kNmseChunk * nwg * sizeof(float));
-  p->ws_bytes = p->off_target + align_up((size_t)p->col_blocks * p->col->col.cols * H * sizeof(float));
+  p->ws_bytes = ws_layout(p, 1).total;
   *out = p;
   return HG_OK;
 }
@@ -565,81 +679,25 @@ hg_status hg_propagate(hg_plan p, const void* in_c64, void* out_c64, int32_t dir
 
 hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumination, float* phase,
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
-  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
-  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
-  if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
-  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
-  if (iterations < 0) return fail(HG_ERR_INVALID_ARGUMENT, "iterations must be >= 0");
-  const int W = p->desc.width, H = p->desc.height;
-  Workspace w = carve(p, workspace);
-  const RowKernels& rk = p->row->row;
-  const ColKernels& ck = p->col->col;
+  const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
+  if (st != HG_OK) return st;
+  return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
+}
 
-  GsRowArgs ra{};
-  ra.field = w.field;
-  ra.illum = illumination;
-  ra.H = H;
-  if (p->desc.propagation == HG_FRESNEL) {
-    ra.q1y = p->q1y;
-    ra.q1x = p->q1x;
-  }
-  ra.slm.lvl_tab = p->lvl_tab;
-  ra.slm.levels = p->levels;
-  ra.slm.inv_delta = p->levels ? (float)((double)p->levels / (2.0 * M_PI)) : 0.0f;
-  ra.slm.inv_delta_f64 = p->levels ? (double)p->levels / (2.0 * M_PI) : 0.0;
-  ra.slm.half_step = p->levels ? make_float2((float)std::cos(M_PI / p->levels), (float)std::sin(M_PI / p->levels))
-                               : make_float2(1.0f, 0.0f);
-  ra.tw = p->tw_row[0];
-  ra.twr = p->tw_row[1];
+size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch) {
+  if (!plan || batch < 1) return 0;
+  return ws_layout(plan, batch).total;
+}
 
-  const int cols = ck.cols;
-  const uint32_t tiled_n = (uint32_t)p->col_blocks * cols * H;
-  hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, target_amp, w.target, H, W, cols,
-                     tiled_n);
-
-  GsColArgs ca{};
-  ca.field = w.field;
-  ca.W = W;
-  ca.H = H;
-  ca.target = w.target;
-  ca.sc = w.sc;
-  ca.tw = p->tw_col[0];
-  ca.twr = p->tw_col[1];
-
-  const int mode = p->levels == 0 ? GS_CONT
-                 : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
-  // steady-state kernel unless the pass needs illumination or produces outputs
-  void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
-
-  if (nmse) enqueue_stats(p, w, target_amp, illumination, 0.0, stream);
-
-  ra.phase0 = phase;
-  ra.phase_out = iterations == 0 ? phase : nullptr;
-  ra.levels_out = iterations == 0 ? levels : nullptr;
-  hipLaunchKernelGGL(rk.gs_start, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
-
-  int chunk0 = 0;  // first state of the pending reduction chunk
-  for (int k = 0; k <= iterations; ++k) {
-    const bool last = k == iterations;
-    if (last && !nmse) break;
-    ca.partials = nmse ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
-    if (last) {
-      hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
-    } else {
-      launch(p, HG_KERNEL_GS_REPLAY, stream, ck.gs_col, p->col_blocks, ck.threads, ck.lds, ca);
-    }
-    if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
-      hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream, w.partials,
-                         p->col_blocks, (const Scalars*)w.sc, nmse + chunk0);
-      chunk0 = k + 1;
-    }
-    if (last) break;
-    ra.phase_out = k == iterations - 1 ? phase : nullptr;
-    ra.levels_out = k == iterations - 1 ? levels : nullptr;
-    void (*gs_row)(GsRowArgs) = (illumination || ra.phase_out) ? rk.gs_row_general : gs_row_hot;
-    launch(p, HG_KERNEL_GS_SLM, stream, gs_row, p->row_blocks, rk.threads, rk.lds, ra);
-  }
-  return launch_status("hg_gs_iterate launch");
+hg_status hg_gs_iterate_batched(hg_plan p, int32_t batch, const float* target_amp, const float* illumination,
+                                float* phase, uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                                hipStream_t stream) {
+  const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
+  if (st != HG_OK) return st;
+  if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
+  if ((size_t)batch * npix(p) > (size_t)UINT32_MAX)
+    return fail(HG_ERR_INVALID_ARGUMENT, "batch * width * height must be below 2^32");
+  return gs_run(p, batch, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
 }
 
 hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, int32_t n_sub, uint8_t* holograms,
@@ -655,7 +713,7 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   Workspace w = carve(p, workspace);
   const RowKernels& rk = p->row->row;
   const ColKernels& ck = p->col->col;
-  if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, stream);
+  if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, w.sc, stream);
 
   OsprRowArgs ra{};
   ra.field = w.field;
@@ -682,8 +740,8 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     launch(p, HG_KERNEL_OSPR_C, stream, rk.ospr_c, p->row_blocks, rk.threads, rk.lds, ra);
   }
   if (nmse)
-    hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, w.partials, p->row_blocks,
-                       (const Scalars*)w.sc, nmse);
+    hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials,
+                       p->row_blocks, (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
   return launch_status("hg_ospr launch");
 }
 

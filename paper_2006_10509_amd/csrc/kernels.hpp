@@ -375,6 +375,16 @@ struct GsRowArgs {
   uint8_t* levels_out;
   const float2* tw;
   const float2* twr;
+  uint32_t px;              // batch: pixels per hologram; item blockIdx.y is offset by blockIdx.y * px
+  // Batch item blockIdx.y of a launch over a stack of same-shape holograms
+  // (gridDim.y items; the illumination is shared).
+  __device__ __forceinline__ void select_item() {
+    const uint32_t off = blockIdx.y * px;
+    field += off;
+    if (phase0) phase0 += off;
+    if (phase_out) phase_out += off;
+    if (levels_out) levels_out += off;
+  }
 };
 
 // SLM-constraint variants of the steady-state row pass.
@@ -396,6 +406,7 @@ __device__ __forceinline__ void write_state(const GsRowArgs& a, uint32_t idx, fl
 // phi0 -> H_0 = A exp(i C(phi0)) -> Q1 H_0 -> row FFT.  Runs once per call.
 template <int N>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a) {
+  a.select_item();
   using C = RowCfg<N>;
   using P = typename C::P;
   using LL = RowLds<N>;
@@ -484,6 +495,7 @@ __device__ __forceinline__ float2 slm_constrain_rt(float2 g, const SlmConstraint
 // returned state, and illuminated runs).
 template <int N, int MODE, bool FRES>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
+  a.select_item();
   using C = RowCfg<N>;
   using P = typename C::P;
   using LL = RowLds<N>;
@@ -551,6 +563,16 @@ struct GsColArgs {
   float* partials;            // one float per workgroup for this state; null -> no NMSE
   const float2* tw;
   const float2* twr;
+  // batch strides of item blockIdx.y: field pixels, tiled-target floats,
+  // partial floats (the Scalars advance by one per item)
+  uint32_t px, target_stride, partial_stride;
+  __device__ __forceinline__ void select_item() {
+    const uint32_t b = blockIdx.y;
+    field += b * px;
+    target += b * target_stride;
+    sc += b;
+    if (partials) partials += b * partial_stride;
+  }
 };
 
 // Replay-plane pass of one state.  Column FFT -> R (the forward FFT2 of the
@@ -563,6 +585,7 @@ struct GsColArgs {
 enum { COL_NMSE = 0, COL_REPLACE = 1, COL_GRAD = 2 };
 template <int N, int MODE>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
+  a.select_item();
   using C = ColCfg<N>;
   using P = typename C::P;
   using LL = ColLds<N>;

@@ -107,11 +107,17 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __r
   }
 }
 
-// nmse[k] = sum_wg partials[k][wg] / denom, one workgroup per state, fixed order.
+// nmse[k] = sum_wg partials[k][wg] / denom, one workgroup per state, fixed
+// order; blockIdx.y selects the batch item (partials, Scalars and nmse
+// advance by partial_stride, 1 and nmse_stride).
 __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce(const float* __restrict__ partials, int nwg,
                                                                const Scalars* __restrict__ sc,
-                                                               float* __restrict__ nmse) {
+                                                               float* __restrict__ nmse, size_t partial_stride,
+                                                               size_t nmse_stride) {
   __shared__ double red[STATS_THREADS];
+  partials += blockIdx.y * partial_stride;
+  sc += blockIdx.y;
+  nmse += blockIdx.y * nmse_stride;
   const float* p = partials + (size_t)blockIdx.x * nwg;
   double s = 0.0;
   for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];

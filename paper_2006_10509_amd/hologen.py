@@ -39,7 +39,8 @@ HG_KERNEL_PROP_ROW = 6
 HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
-            "hg_propagate", "hg_gs_iterate", "hg_ospr", "hg_grad_workspace_bytes", "hg_grad",
+            "hg_propagate", "hg_gs_iterate", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
+            "hg_ospr", "hg_grad_workspace_bytes", "hg_grad",
             "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
 
 
@@ -87,6 +88,10 @@ def library() -> ctypes.CDLL:
     lib.hg_propagate.restype = i32
     lib.hg_gs_iterate.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.hg_gs_iterate.restype = i32
+    lib.hg_workspace_bytes_batched.argtypes = [vp, i32]
+    lib.hg_workspace_bytes_batched.restype = sz
+    lib.hg_gs_iterate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.hg_gs_iterate_batched.restype = i32
     lib.hg_ospr.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr.restype = i32
     lib.hg_grad_workspace_bytes.argtypes = [vp, i32]
@@ -232,6 +237,25 @@ def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
         _ptr(levels, torch.uint8, shape, "levels", optional=True),
         _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
         int(iterations), _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+
+
+def workspace_bytes_batched(plan: Plan, batch: int) -> int:
+    return int(library().hg_workspace_bytes_batched(plan.handle, batch))
+
+
+def hg_gs_iterate_batched(plan: Plan, target_amp, phase, iterations: int, workspace,
+                          illumination=None, levels=None, nmse=None, stream=None) -> None:
+    """GS on a [batch, H, W] stack of same-shape holograms, one launch per pass."""
+    import torch
+    batch = int(phase.shape[0])
+    shape = (batch, plan.height, plan.width)
+    _check(library().hg_gs_iterate_batched(
+        plan.handle, batch, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape[1:], "illumination", optional=True),
+        _ptr(phase, torch.float32, shape, "phase"),
+        _ptr(levels, torch.uint8, shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (batch, iterations + 1), "nmse", optional=True),
+        int(iterations), _workspace(workspace, workspace_bytes_batched(plan, batch)), _stream(stream)))
 
 
 def hg_ospr(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=None,

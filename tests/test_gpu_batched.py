@@ -1,0 +1,100 @@
+"""Batched GS (hg_gs_iterate_batched): one launch per pass over a stack of
+same-shape holograms.  Bar: bitwise equal to hg_gs_iterate on each item
+(same kernels, one more grid dimension), which the single-hologram parity
+tests tie to the oracle; one item of a batch is also checked against the
+oracle directly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_10509_amd import hologen as hg
+from paper_2006_10509_amd import workloads as wl
+from gpu_util import dev, host, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def stack(h, w, batch, seed0):
+    ts, ps = zip(*[wl.target_and_phase(h, w, seed0 + i) for i in range(batch)])
+    return np.stack(ts), np.stack(ps)
+
+
+def make_plan(h, w, levels, fresnel):
+    mod = hg.HG_PHASE_QUANTISED if levels else hg.HG_PHASE
+    if fresnel:
+        return hg.Plan(w, h, hg.HG_FRESNEL, 532e-9, 8e-6, 0.5, mod, levels)
+    return hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, mod, levels)
+
+
+def run_batched(plan, targets, phases, iters, illum=None):
+    torch = torch_mod()
+    b = targets.shape[0]
+    ph = dev(phases.copy())
+    lv = torch.zeros(targets.shape, dtype=torch.uint8, device="cuda")
+    nm = torch.zeros((b, iters + 1), dtype=torch.float32, device="cuda")
+    ws = torch.empty(hg.workspace_bytes_batched(plan, b), dtype=torch.uint8, device="cuda")
+    hg.hg_gs_iterate_batched(plan, dev(targets), ph, iters, ws, illumination=None if illum is None else dev(illum),
+                             levels=lv, nmse=nm)
+    return host(ph), host(lv), host(nm)
+
+
+def run_single(plan, target, phase, iters, illum=None):
+    torch = torch_mod()
+    ph = dev(phase.copy())
+    lv = torch.zeros(target.shape, dtype=torch.uint8, device="cuda")
+    nm = torch.zeros(iters + 1, dtype=torch.float32, device="cuda")
+    hg.hg_gs_iterate(plan, dev(target), ph, iters, plan.workspace(),
+                     illumination=None if illum is None else dev(illum), levels=lv, nmse=nm)
+    return host(ph), host(lv), host(nm)
+
+
+@pytest.mark.parametrize("h,w,batch,levels,fresnel,iters", [
+    (256, 256, 5, 8, True, 12),
+    (512, 512, 3, 4, False, 6),
+    (1080, 1920, 2, 4, False, 3),
+    (120, 90, 4, 0, True, 7),
+    (2048, 2048, 2, 4, False, 2),
+])
+def test_batched_equals_single_calls_bitwise(h, w, batch, levels, fresnel, iters):
+    print(f"batched {batch} x {h}x{w} L={levels} fresnel={fresnel} it={iters}", flush=True)
+    plan = make_plan(h, w, levels, fresnel)
+    targets, phases = stack(h, w, batch, 100 + h)
+    bp, bl, bn = run_batched(plan, targets, phases, iters)
+    for i in range(batch):
+        sp, sl, sn = run_single(plan, targets[i], phases[i], iters)
+        assert np.array_equal(bp[i], sp) and np.array_equal(bl[i], sl) and np.array_equal(bn[i], sn), i
+
+
+def test_batched_shared_illumination_and_zero_iterations():
+    h, w, batch = 128, 128, 3
+    plan = make_plan(h, w, 8, True)
+    targets, phases = stack(h, w, batch, 7)
+    yy, xx = np.mgrid[0:h, 0:w]
+    illum = np.exp(-((yy - h / 2) ** 2 + (xx - w / 2) ** 2) / (2 * 40.0 ** 2)).astype(np.float32)
+    for iters in (0, 4):
+        bp, bl, bn = run_batched(plan, targets, phases, iters, illum)
+        for i in range(batch):
+            sp, sl, sn = run_single(plan, targets[i], phases[i], iters, illum)
+            assert np.array_equal(bp[i], sp) and np.array_equal(bl[i], sl) and np.array_equal(bn[i], sn)
+
+
+def test_batch_item_against_oracle():
+    h, w, batch, iters = 512, 512, 4, 5
+    plan = make_plan(h, w, 4, False)
+    targets, phases = stack(h, w, batch, 40)
+    _, _, bn = run_batched(plan, targets, phases, iters)
+    i = batch - 1
+    ref = oracle.gs_iterate(targets[i], phases[i], iters, levels=4)
+    rel = np.abs(bn[i] - np.array(ref["nmse"])) / np.array(ref["nmse"])
+    assert rel.max() <= 1e-4
+
+
+def test_batched_argument_checks():
+    torch = torch_mod()
+    plan = make_plan(64, 64, 4, False)
+    targets, phases = stack(64, 64, 2, 1)
+    ws = torch.empty(hg.workspace_bytes_batched(plan, 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):   # workspace sized for one item
+        hg.hg_gs_iterate_batched(plan, dev(targets), dev(phases), 2, ws)
+    assert hg.workspace_bytes_batched(plan, 1) == plan.workspace_bytes()
+    assert hg.workspace_bytes_batched(plan, 0) == 0
