@@ -31,17 +31,24 @@ namespace hg {
 
 // ---------------------------------------------------------------------------
 // complex helpers (float2: .x real, .y imaginary)
+//
+// Every sum of two products is written with an explicit fmaf: left to the
+// compiler, a*b + c*d may be contracted as fma(a, b, c*d) or fma(c, d, a*b)
+// depending on the surrounding code, so the same arithmetic in two kernels
+// (a loop's start pass and its steady-state pass, say) could round
+// differently.  With the contraction fixed here, a state computed by any
+// sequence of calls is bitwise the same.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cmulconj(float2 a, float2 b) {  // a * conj(b)
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float cnorm(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
 // multiply by DIR * i  (DIR = -1: forward kernel exp(-...), +1: inverse)
 template <int DIR> __device__ __forceinline__ float2 mul_dir_i(float2 a) {
@@ -158,10 +165,10 @@ template <int DIR> __device__ __forceinline__ void dft5(float2* a) {
                           a[0].y + HG_COS_2PI_5 * t1.y + HG_COS_4PI_5 * t2.y);
   float2 b2 = make_float2(a[0].x + HG_COS_4PI_5 * t1.x + HG_COS_2PI_5 * t2.x,
                           a[0].y + HG_COS_4PI_5 * t1.y + HG_COS_2PI_5 * t2.y);
-  float2 e1 = mul_dir_i<DIR>(make_float2(HG_SIN_2PI_5 * d1.x + HG_SIN_4PI_5 * d2.x,
-                                         HG_SIN_2PI_5 * d1.y + HG_SIN_4PI_5 * d2.y));
-  float2 e2 = mul_dir_i<DIR>(make_float2(HG_SIN_4PI_5 * d1.x - HG_SIN_2PI_5 * d2.x,
-                                         HG_SIN_4PI_5 * d1.y - HG_SIN_2PI_5 * d2.y));
+  float2 e1 = mul_dir_i<DIR>(make_float2(fmaf(HG_SIN_2PI_5, d1.x, HG_SIN_4PI_5 * d2.x),
+                                         fmaf(HG_SIN_2PI_5, d1.y, HG_SIN_4PI_5 * d2.y)));
+  float2 e2 = mul_dir_i<DIR>(make_float2(fmaf(HG_SIN_4PI_5, d1.x, -(HG_SIN_2PI_5 * d2.x)),
+                                         fmaf(HG_SIN_4PI_5, d1.y, -(HG_SIN_2PI_5 * d2.y))));
   a[0] = cadd(a[0], cadd(t1, t2));
   a[1] = cadd(b1, e1);
   a[4] = csub(b1, e1);

@@ -622,7 +622,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
     const float2 R = v[s];
     const float tv = tgt[s];
     const float I = cnorm(R);
-    const float d = I * sa - tv * tv * sb;
+    const float d = fmaf(I, sa, -(tv * tv * sb));
     acc = fmaf(d, d, acc);
     if constexpr (MODE == COL_REPLACE) {
       const float k = tv * rsqrtf(I);
@@ -707,15 +707,15 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
     float2 V = make_float2(cs, sn);
     if (fres) V = cmul(V, cmul(qy, qx.at(s, x)));
     const float2 G = v[s];
-    const float g = ac[s] + 2.0f * (V.x * G.y - V.y * G.x);
+    const float g = fmaf(2.0f, fmaf(V.x, G.y, -(V.y * G.x)), ac[s]);
     if (!a.last) {
       stg(a.acc, i, g);
       return;
     }
     if (a.grad_out) stg(a.grad_out, i, g);
     if (adam) {
-      const float m1 = a.beta1 * mm[s] + (1.0f - a.beta1) * g;
-      const float v1 = a.beta2 * vv[s] + (1.0f - a.beta2) * g * g;
+      const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g);
+      const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g * g);
       stg(a.m, i, m1);
       stg(a.v, i, v1);
       stg(a.phase, i, ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps));
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     float I = cnorm(v[s]) + prev[s];
     if (a.last) {
       I *= a.inv_nsub;
-      const float d = I * sa - tg[s] * tg[s] * sb;
+      const float d = fmaf(I, sa, -(tg[s] * tg[s] * sb));
       acc = fmaf(d, d, acc);
     }
     if (rt.live) stg(a.intensity, orow + wrap_add<N>(k, N / 2), I);

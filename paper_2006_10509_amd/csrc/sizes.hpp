@@ -30,22 +30,27 @@ template <int N> struct ColCfg;
     static constexpr bool WAVE_SYNC = (C_ * T_ <= 64);                   \
   };
 
+// The shapes of lengths 512, 1024, 1080, 1920 and 2048 were chosen by timing
+// the GS loop on MI355X over candidate team sizes, radix orders and column
+// tile widths (single holograms and same-shape batches); the rest are
+// untuned defaults.  Wider column tiles (C = 8: 64-byte row segments) win
+// where the frame still gives every CU a tile.
 //          N     rows/WG  T    radices
 HG_ROW_CFG(16,    64,     4,   4, 4)
 HG_ROW_CFG(32,    32,     8,   4, 2, 4)
 HG_ROW_CFG(64,    32,     8,   8, 8)
 HG_ROW_CFG(128,   16,    16,   8, 2, 8)
 HG_ROW_CFG(256,   16,    16,   16, 16)
-HG_ROW_CFG(512,    4,    64,   8, 8, 8)
+HG_ROW_CFG(512,   2,    64,   8, 8, 8)
 HG_ROW_CFG(1024,   2,   128,   8, 4, 4, 8)
-HG_ROW_CFG(2048,   2,    64,   16, 8, 16)
+HG_ROW_CFG(2048,   2,   128,   16, 8, 16)
 HG_ROW_CFG(4096,   2,   128,   16, 16, 16)
 HG_ROW_CFG(24,    32,     8,   8, 3)
 HG_ROW_CFG(60,    16,    16,   4, 3, 5)
 HG_ROW_CFG(90,    16,    16,   2, 3, 3, 5)
 HG_ROW_CFG(120,   16,    16,   8, 3, 5)
 HG_ROW_CFG(1080,   4,    64,   8, 3, 3, 3, 5)
-HG_ROW_CFG(1920,   4,    64,   16, 8, 3, 5)
+HG_ROW_CFG(1920,   2,   128,   16, 8, 3, 5)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
@@ -53,15 +58,15 @@ HG_COL_CFG(32,    16,     8,   4, 2, 4)
 HG_COL_CFG(64,    16,     8,   8, 8)
 HG_COL_CFG(128,   16,    16,   8, 2, 8)
 HG_COL_CFG(256,    8,    16,   16, 16)
-HG_COL_CFG(512,    4,    64,   8, 8, 8)
+HG_COL_CFG(512,   8,    64,   8, 8, 8)
 HG_COL_CFG(1024,   4,   128,   8, 4, 4, 8)
-HG_COL_CFG(2048,   4,    64,   16, 8, 16)
+HG_COL_CFG(2048,   8,    64,   16, 8, 16)
 HG_COL_CFG(4096,   2,   128,   16, 16, 16)
 HG_COL_CFG(24,    16,     8,   8, 3)
 HG_COL_CFG(60,    16,    16,   4, 3, 5)
 HG_COL_CFG(90,    16,    16,   2, 3, 3, 5)
 HG_COL_CFG(120,   16,    16,   8, 3, 5)
-HG_COL_CFG(1080,   4,    64,   8, 3, 3, 3, 5)
+HG_COL_CFG(1080,   8,   120,   8, 3, 3, 3, 5)
 HG_COL_CFG(1920,   4,    64,   16, 8, 3, 5)
 
 // X-macro over every compiled length (used for host dispatch tables).
