@@ -38,13 +38,13 @@ from .constraints import (quantise_level, quantise_phase_level, phase_only,
                           replace_amplitude, binarise)
 from .metrics import nmse
 from .gs import gs_iterate
-from .ospr import ospr
+from .ospr import ospr, ospr_pairs
 from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
     "fresnel_chirp", "fresnel_geometry", "propagate",
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
-    "binarise", "nmse", "gs_iterate", "ospr",
+    "binarise", "nmse", "gs_iterate", "ospr", "ospr_pairs",
     "source_chirp", "loss_and_gradient", "adam_update", "grad_descent",
 ]

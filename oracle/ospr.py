@@ -12,6 +12,10 @@ for each subframe n
 
 and the eye sees the time average I_avg = (1/N) sum_n I_n, reported in centred
 order as fftshift(I_avg) together with NMSE(fftshift(I_avg), T_amp^2).
+
+Real and imaginary pairs (ospr_pairs): one inverse transform G_n gives two
+subframes, h_2n from the sign of Re G_n and h_2n+1 from the sign of Im G_n
+(the same >= 0 rule), and the average runs over all 2N subframes.
 """
 from __future__ import annotations
 
@@ -40,4 +44,25 @@ def ospr(target_amp: np.ndarray, sub_phases: np.ndarray) -> dict:
         lev[n] = (h < 0).astype(np.uint8)
         acc += np.abs(fft2(h)) ** 2
     avg = fftshift(acc / n_sub)
+    return {"levels": lev, "intensity": avg, "nmse": nmse_fn(avg, t_amp * t_amp)}
+
+
+def ospr_pairs(target_amp: np.ndarray, sub_phases: np.ndarray) -> dict:
+    """target_amp [H][W] centred; sub_phases [N][H][W] centred, one per pair.
+
+    Returns levels [2N][H][W] (subframe 2n from Re G_n, 2n + 1 from Im G_n),
+    the centred average intensity over the 2N subframes and its NMSE.
+    """
+    t_amp = np.asarray(target_amp, dtype=np.float64)
+    thetas = np.asarray(sub_phases, dtype=np.float64)
+    n_pairs = thetas.shape[0]
+    acc = np.zeros(t_amp.shape)
+    lev = np.empty((2 * n_pairs,) + t_amp.shape, dtype=np.uint8)
+    for n in range(n_pairs):
+        g = ifft2(ifftshift(t_amp * np.exp(1j * thetas[n])))
+        for k, part in enumerate((g.real, g.imag)):
+            h = np.where(part >= 0.0, 1.0, -1.0)
+            lev[2 * n + k] = (h < 0).astype(np.uint8)
+            acc += np.abs(fft2(h)) ** 2
+    avg = fftshift(acc / (2 * n_pairs))
     return {"levels": lev, "intensity": avg, "nmse": nmse_fn(avg, t_amp * t_amp)}

@@ -3,7 +3,9 @@
 A 2x2 example worked by hand, the centro-symmetry of the replay of a real
 (binary) hologram, Parseval's sum sum I = N_px^2 for +-1 holograms, the
 single-subframe case against numpy's inverse FFT, and independence of the
-subframe order.
+subframe order.  Real/imaginary pairs: a pair with phase theta is the plain
+method on the two phases theta and theta - pi/2 (Re(-i G) = Im G), and its
+replay keeps the centro-symmetry and the energy of plain OSPR.
 """
 import numpy as np
 
@@ -59,3 +61,32 @@ def test_subframe_order_independent():
     b = oracle.ospr(t, th[::-1])
     assert np.allclose(a["intensity"], b["intensity"], rtol=1e-12, atol=1e-9)
     assert abs(a["nmse"] - b["nmse"]) <= 1e-12
+
+
+def test_pairs_equal_plain_ospr_on_quarter_turned_phases():
+    rng = np.random.default_rng(34)
+    h, w = 24, 40
+    t = np.sqrt(rng.uniform(0, 1, (h, w)))
+    th = rng.uniform(0, 2 * np.pi, (3, h, w))
+    pairs = oracle.ospr_pairs(t, th)
+    expanded = np.stack([p for n in range(3) for p in (th[n], th[n] - np.pi / 2)])
+    plain = oracle.ospr(t, expanded)
+    assert pairs["levels"].shape == (6, h, w)
+    # the two routes round differently only at exact ties
+    g = [np.fft.ifft2(np.fft.ifftshift(t * np.exp(1j * th[n]))) for n in range(3)]
+    parts = np.stack([p for gn in g for p in (gn.real, gn.imag)])
+    clear = np.abs(parts) > 1e-12 * np.abs(parts).max()
+    assert np.array_equal(pairs["levels"][clear], plain["levels"][clear])
+    assert np.allclose(pairs["intensity"], plain["intensity"], rtol=1e-12, atol=1e-9)
+    assert abs(pairs["nmse"] - plain["nmse"]) <= 1e-12
+
+
+def test_pairs_symmetry_and_energy():
+    rng = np.random.default_rng(35)
+    h, w = 32, 48
+    t = np.sqrt(rng.uniform(0, 1, (h, w)))
+    out = oracle.ospr_pairs(t, rng.uniform(0, 2 * np.pi, (2, h, w)))
+    i_c = out["intensity"]
+    mirrored = i_c[(-np.arange(h)) % h][:, (-np.arange(w)) % w]
+    assert np.abs(mirrored - i_c).max() <= 1e-9 * i_c.max()
+    assert abs(i_c.sum() - (h * w) ** 2) <= 1e-12 * (h * w) ** 2
