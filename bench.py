@@ -261,6 +261,38 @@ def batched_mix(hg, wl, torch, stream, inputs, iterations: int = 50) -> dict:
             "launches": f"{len(shapes)} batched calls vs {n} single calls"}
 
 
+def ospr_2048(hg, wl, torch, stream) -> dict:
+    """The 2048x2048 binary OSPR workload (24 subframes): plain OSPR (one
+    inverse transform per subframe) against real/imaginary pairs (two
+    subframes per inverse transform, 12 pairs), subframes/s."""
+    w = wl.OSPR_2048
+    t = torch.from_numpy(w.target()).cuda()
+    th = torch.from_numpy(w.subframe_phases()).cuda()
+    plan = hg.Plan(w.width, w.height, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_BINARY_PHASE, 2)
+    ws = plan.workspace()
+    inten = torch.empty((w.height, w.width), dtype=torch.float32, device="cuda")
+    nm = torch.empty(1, dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(5):
+            f()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / 5
+
+    plain_ms = timed(lambda: hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream))
+    plain_nmse = float(nm.item())
+    pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, nmse=nm, stream=stream))
+    return {"workload": w.name, "subframes": w.subframes, "plain_ms": round(plain_ms, 3),
+            "plain_subframes_per_s": round(w.subframes / (plain_ms * 1e-3), 1), "plain_nmse": plain_nmse,
+            "pairs_ms": round(pair_ms, 3), "pairs_subframes_per_s": round(w.subframes / (pair_ms * 1e-3), 1),
+            "pairs_nmse": float(nm.item())}
+
+
 def rocfft_reference(torch, stream, n: int = 1024, reps: int = 200) -> dict:
     """torch.fft (rocFFT) forward + inverse 2D transform of one n x n complex64
     field, back to back: a vendor-library reference point, not part of the path."""
@@ -387,6 +419,8 @@ def main() -> int:
         mix = batched_mix(hg, wl, torch, stream, mixed)
         log(f"  {mix}")
 
+    osp = ospr_2048(hg, wl, torch, stream)
+    log(f"OSPR 2048: {osp}")
     rf = rocfft_reference(torch, stream)
     log(f"rocFFT reference: {rf}")
 
@@ -404,7 +438,7 @@ def main() -> int:
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
                       "target_seed": w.target_seed, "phase_seed": w.phase_seed},
            "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
-           "batched_mix": mix, "rocfft_reference": rf}
+           "batched_mix": mix, "ospr": osp, "rocfft_reference": rf}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -153,6 +153,19 @@ hg_status hg_gs_iterate_batched(hg_plan plan, int32_t batch, const float* target
 hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_sub,
                   uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
 
+/* OSPR with real and imaginary subframe pairs, binary phase, on a HG_FOURIER
+ * plan: one inverse transform per pair gives two subframes,
+ *   G_n = IFFT2(ifftshift(target_amp exp(i sub_phase[n]))),
+ *   h_2n = sign(Re G_n), h_2n+1 = sign(Im G_n)   (>= 0 -> +1 / level 0),
+ *   intensity = fftshift(mean over the 2 n_pairs subframes of |FFT2 h|^2),
+ *   nmse[0] = NMSE(intensity, target_amp^2).
+ * Both subframes of a pair share one forward transform of h_2n + i h_2n+1;
+ * their intensities are separated through the Hermitian symmetry of real
+ * holograms.  holograms [2 n_pairs][H][W] uint8 or NULL; other arguments as
+ * hg_ospr; n_pairs >= 1. */
+hg_status hg_ospr_pairs(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_pairs,
+                        uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
+
 /* Gradient-descent hologram optimisation: the method added beyond the
  * paper's library, whose further algorithms are left to future work (Sec. 8).
  * The parameter is the continuous SLM phase phi; each of the n_planes replay

@@ -93,6 +93,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->col.gs_col, e->col.lds));
   chk(allow_lds(e->col.gs_col_nmse, e->col.lds));
   chk(allow_lds(e->col.ospr_b, e->col.lds));
+  chk(allow_lds(e->col.ospr_b_pair, e->col.lds));
   chk(allow_lds(e->row.grad_row, e->row.lds));
   chk(allow_lds(e->col.grad_col, e->col.lds));
   return err;
@@ -743,6 +744,59 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials,
                        p->row_blocks, (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
   return launch_status("hg_ospr launch");
+}
+
+hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_phase, int32_t n_pairs,
+                        uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (p->desc.propagation != HG_FOURIER) return fail(HG_ERR_INVALID_ARGUMENT, "hg_ospr_pairs needs a HG_FOURIER plan");
+  if (!target_amp || !sub_phase || !intensity)
+    return fail(HG_ERR_INVALID_ARGUMENT, "target_amp, sub_phase and intensity are required");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (n_pairs < 1) return fail(HG_ERR_INVALID_ARGUMENT, "n_pairs must be >= 1");
+  const int W = p->desc.width, H = p->desc.height;
+  const size_t n = npix(p);
+  Workspace w = carve(p, workspace);
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+  if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, w.sc, stream);
+
+  OsprRowArgs ra{};
+  ra.field = w.field;
+  ra.H = H;
+  ra.target = target_amp;
+  ra.intensity = intensity;
+  ra.sc = w.sc;
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
+  OsprColArgs ca{};
+  ca.field = w.field;
+  ca.W = W;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
+  for (int s = 0; s < n_pairs; ++s) {
+    ra.theta = sub_phase + (size_t)s * n;
+    ra.first = s == 0;
+    ra.last = 0;        // sums only: the finish kernel averages and scores
+    ra.partials = nullptr;
+    ca.levels = holograms ? holograms + (size_t)(2 * s) * n : nullptr;
+    ca.levels_im = holograms ? holograms + (size_t)(2 * s + 1) * n : nullptr;
+    launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
+    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b_pair, p->col_blocks, ck.threads, ck.lds, ca);
+    launch(p, HG_KERNEL_OSPR_C, stream, rk.ospr_c, p->row_blocks, rk.threads, rk.lds, ra);
+  }
+  // one partial per block: at most PAIR_MAX_BLOCKS, and never more than the
+  // workspace's partial buffer holds (kNmseChunk x workgroups of a pass)
+  const size_t cap = ws_layout(p, 1).partial_stride;
+  size_t nb = (n + PAIR_THREADS - 1) / PAIR_THREADS;
+  if (nb > (size_t)PAIR_MAX_BLOCKS) nb = PAIR_MAX_BLOCKS;
+  if (nb > cap) nb = cap;
+  hipLaunchKernelGGL(k_ospr_pair_finish, dim3((unsigned)nb), dim3(PAIR_THREADS), 0, stream, intensity, target_amp, H, W,
+                     (float)(1.0 / (4.0 * n_pairs)), (const Scalars*)w.sc, nmse ? w.partials : nullptr);
+  if (nmse)
+    hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials, (int)nb,
+                       (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
+  return launch_status("hg_ospr_pairs launch");
 }
 
 size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes) {

@@ -777,13 +777,17 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
 struct OsprColArgs {
   float2* field;
   int W;
-  uint8_t* levels;   // [H][W] of this subframe, natural SLM order; may be null
+  uint8_t* levels;     // [H][W] of this subframe, natural SLM order; may be null
+  uint8_t* levels_im;  // pairs: [H][W] of the subframe binarised from Im G; may be null
   const float2* tw;
   const float2* twr;
 };
 
 // Pass B: inverse column FFT -> h = sign(Re G) -> level -> forward column FFT of h.
-template <int N>
+// PAIR: two subframes from one G, h_re = sign(Re G) and h_im = sign(Im G), and
+// the column FFT of the complex field h_re + i h_im carries both (pass C and
+// k_ospr_pair_finish separate their intensities).
+template <int N, bool PAIR>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   using C = ColCfg<N>;
   using P = typename C::P;
@@ -805,10 +809,17 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   if constexpr (TW::USES_LDS) __syncthreads();
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const bool wl = live && a.levels;
+  const bool wl_im = PAIR && live && a.levels_im;
   for_layout<LF>(t, [&](int s, int y) {
     const bool neg = !(v[s].x >= 0.0f);
     if (wl) stg(a.levels, (uint32_t)y * a.W + x, (uint8_t)(neg ? 1 : 0));
-    v[s] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
+    float im = 0.0f;
+    if constexpr (PAIR) {
+      const bool neg_im = !(v[s].y >= 0.0f);
+      if (wl_im) stg(a.levels_im, (uint32_t)y * a.W + x, (uint8_t)(neg_im ? 1 : 0));
+      im = neg_im ? -1.0f : 1.0f;
+    }
+    v[s] = make_float2(neg ? -1.0f : 1.0f, im);
   });
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
@@ -884,6 +895,7 @@ struct ColKernels {
   void (*gs_col_nmse)(GsColArgs);
   void (*grad_col)(GsColArgs);
   void (*ospr_b)(OsprColArgs);
+  void (*ospr_b_pair)(OsprColArgs);
   int cols, threads;
   size_t lds;
 };
@@ -929,7 +941,7 @@ LengthEntry make_length_entry() {
   e.row.threads = RowCfg<N>::THREADS;
   e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
-           k_gs_col<N, COL_GRAD>, k_ospr_b<N>,
+           k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
   using PR = typename RowCfg<N>::P;
   using PC = typename ColCfg<N>::P;

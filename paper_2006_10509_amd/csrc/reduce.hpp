@@ -142,4 +142,44 @@ __global__ __launch_bounds__(STATS_THREADS) void k_loss_reduce(const float* __re
   if (threadIdx.x == 0) loss[blockIdx.x] = (float)total;
 }
 
+// OSPR pairs, after the last pass C: S (centred) holds sum_n |H_n|^2 with
+// H_n = FFT2(h_re + i h_im) of real +-1 holograms.  Since |FFT2 h_re(k)|^2 +
+// |FFT2 h_im(k)|^2 = (|H(k)|^2 + |H(-k)|^2) / 2, the mean over the 2N real
+// subframes is I(k) = (S(k) + S(-k)) * scale with scale = 1 / (4 N).  -k is
+// the mirrored pixel ((H - y) % H, (W - x) % W) in centred order.  In place:
+// every mirror pair is read and written by the thread of its first pixel.
+// With partials, also the NMSE partial sums against T^2 (as pass C does).
+constexpr int PAIR_THREADS = 256;
+constexpr int PAIR_MAX_BLOCKS = 1024;
+__global__ __launch_bounds__(PAIR_THREADS) void k_ospr_pair_finish(float* __restrict__ intensity,
+                                                                   const float* __restrict__ target, int H, int W,
+                                                                   float scale, const Scalars* __restrict__ sc,
+                                                                   float* __restrict__ partials) {
+  __shared__ double red[PAIR_THREADS];
+  const size_t n = (size_t)H * W;
+  const float sa = partials ? sc->a : 0.0f;
+  const float sb = partials ? sc->b : 0.0f;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * PAIR_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * PAIR_THREADS) {
+    const int y = (int)(i / W), x = (int)(i % W);
+    const size_t j = (size_t)((H - y) % H) * W + (size_t)((W - x) % W);
+    if (j < i) continue;
+    const float v = (intensity[i] + intensity[j]) * scale;
+    intensity[i] = v;
+    if (j != i) intensity[j] = v;
+    if (partials) {
+      const float ti = target[i], di = fmaf(v, sa, -(ti * ti * sb));
+      acc += (double)di * di;
+      if (j != i) {
+        const float tj = target[j], dj = fmaf(v, sa, -(tj * tj * sb));
+        acc += (double)dj * dj;
+      }
+    }
+  }
+  if (partials) {
+    acc = block_sum_f64<PAIR_THREADS>(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = (float)acc;
+  }
+}
+
 }  // namespace hg

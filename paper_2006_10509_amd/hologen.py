@@ -40,7 +40,7 @@ HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
             "hg_propagate", "hg_gs_iterate", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
-            "hg_ospr", "hg_grad_workspace_bytes", "hg_grad",
+            "hg_ospr", "hg_ospr_pairs", "hg_grad_workspace_bytes", "hg_grad",
             "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
 
 
@@ -94,6 +94,8 @@ def library() -> ctypes.CDLL:
     lib.hg_gs_iterate_batched.restype = i32
     lib.hg_ospr.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr.restype = i32
+    lib.hg_ospr_pairs.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.hg_ospr_pairs.restype = i32
     lib.hg_grad_workspace_bytes.argtypes = [vp, i32]
     lib.hg_grad_workspace_bytes.restype = sz
     lib.hg_grad.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp]
@@ -237,6 +239,22 @@ def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
         _ptr(levels, torch.uint8, shape, "levels", optional=True),
         _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
         int(iterations), _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+
+
+def hg_ospr_pairs(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=None,
+                  nmse=None, stream=None) -> None:
+    """OSPR with two subframes (Re and Im) per inverse transform; holograms is
+    [2 n_pairs, H, W] or None."""
+    import torch
+    shape = (plan.height, plan.width)
+    n_pairs = int(sub_phase.shape[0])
+    _check(library().hg_ospr_pairs(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(sub_phase, torch.float32, (n_pairs,) + shape, "sub_phase"), n_pairs,
+        _ptr(holograms, torch.uint8, (2 * n_pairs,) + shape, "holograms", optional=True),
+        _ptr(intensity, torch.float32, shape, "intensity"),
+        _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
+        _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
 
 
 def workspace_bytes_batched(plan: Plan, batch: int) -> int:

@@ -79,3 +79,65 @@ def test_ospr_optional_outputs():
     a = run_ospr(t, thetas)
     b = run_ospr(t, thetas, want_holo=False, want_nmse=False)
     assert np.array_equal(a[0], b[0])
+
+
+# ---------------------------------------------------------------------------
+# real / imaginary subframe pairs (hg_ospr_pairs) against oracle.ospr_pairs
+# ---------------------------------------------------------------------------
+def run_pairs(t, thetas, want_holo=True):
+    torch = torch_mod()
+    n_pairs, h, w = thetas.shape
+    plan = hg.Plan(w, h, hg.HG_FOURIER, 0, 0, 0, hg.HG_BINARY_PHASE, 2)
+    inten = torch.empty((h, w), dtype=torch.float32, device="cuda")
+    holo = torch.empty((2 * n_pairs, h, w), dtype=torch.uint8, device="cuda") if want_holo else None
+    nm = torch.empty(1, dtype=torch.float32, device="cuda")
+    hg.hg_ospr_pairs(plan, dev(t), dev(thetas), inten, plan.workspace(), holograms=holo, nmse=nm)
+    return host(inten), None if holo is None else host(holo), host(nm)[0]
+
+
+@pytest.mark.parametrize("h,w,n_pairs", [(256, 256, 3), (90, 120, 2), (1080, 1920, 1), (512, 512, 4), (24, 60, 2)])
+def test_ospr_pairs_match_oracle(h, w, n_pairs):
+    print(f"ospr pairs {h}x{w} n_pairs={n_pairs}", flush=True)
+    t = wl.target_amplitude(h, w, seed=h + w + 1)
+    thetas = np.stack([wl.uniform_phase(h, w, seed=80 + n) for n in range(n_pairs)])
+    inten, holo, nm = run_pairs(t, thetas)
+    ref = oracle.ospr_pairs(t, thetas)
+    flips = 0
+    for n in range(n_pairs):
+        g = oracle.ifft2(oracle.ifftshift(t.astype(np.float64) * np.exp(1j * thetas[n].astype(np.float64))))
+        for k, part in enumerate((g.real, g.imag)):
+            band = np.abs(part) < 1e-5 * np.abs(g)
+            diff = holo[2 * n + k] != ref["levels"][2 * n + k]
+            assert not (diff & ~band).any(), (n, k)
+            flips += int(diff.sum())
+    npx = h * w
+    tol = 1e-5 + 4.0 * flips / (np.sqrt(npx) * 2 * n_pairs)
+    assert rel_l2(inten, ref["intensity"]) <= tol
+    assert abs(nm - ref["nmse"]) <= 1e-4 * ref["nmse"] + (tol if flips else 0.0)
+
+
+def test_ospr_pairs_equal_plain_gpu_ospr_on_quarter_turned_phases():
+    """A pair with phase theta is the plain method on theta and theta - pi/2:
+    same levels (outside ties) and the same average intensity."""
+    h, w = 256, 256
+    t = wl.target_amplitude(h, w, seed=4)
+    thetas = np.stack([wl.uniform_phase(h, w, seed=90 + n) for n in range(2)])
+    expanded = np.stack([p for th in thetas for p in (th, th - np.float32(np.pi / 2))]).astype(np.float32)
+    pi, ph, _ = run_pairs(t, thetas)
+    qi, qh, _ = run_ospr(t, expanded)
+    assert (ph != qh).mean() <= 1e-4
+    assert rel_l2(pi, qi) <= 1e-4
+
+
+def test_ospr_pairs_full_size_properties():
+    """2048x2048 with 12 pairs (the 24 subframes of the OSPR workload)."""
+    w = wl.OSPR_2048
+    t = w.target()
+    thetas = w.subframe_phases(12)
+    inten, holo, nm = run_pairs(t, thetas, want_holo=True)
+    npx = w.height * w.width
+    assert abs(inten.astype(np.float64).sum() - npx ** 2) <= 1e-5 * npx ** 2
+    mirrored = inten[(-np.arange(w.height)) % w.height][:, (-np.arange(w.width)) % w.width]
+    assert np.array_equal(mirrored, inten)       # the finish pass writes each mirror pair once
+    assert set(np.unique(holo).tolist()) <= {0, 1}
+    assert 0.0 < nm < 1.0
