@@ -27,6 +27,8 @@ step by step in the order the method performs it:
   ospr.py         One-Step Phase-Retrieval (Cable, Buckley et al. 2004).
   grad.py         gradient-descent hologram optimisation: multi-plane NMSE
                   loss, its Wirtinger gradient and Adam (Kingma & Ba 2015).
+  search.py       single-pixel direct binary search and simulated annealing
+                  (the paper's HoloGenAlgDSCuda / HoloGenAlgSACuda, Sec. 7.3).
 
 Readings taken where the paper is silent are listed in the design doc.  Every
 function is pinned by ``tests/test_oracle_*.py`` against closed forms,
@@ -40,11 +42,12 @@ from .metrics import nmse
 from .gs import gs_iterate
 from .ospr import ospr, ospr_pairs
 from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
+from .search import pixel_search
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
     "fresnel_chirp", "fresnel_geometry", "propagate",
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
     "binarise", "nmse", "gs_iterate", "ospr", "ospr_pairs",
-    "source_chirp", "loss_and_gradient", "adam_update", "grad_descent",
+    "source_chirp", "loss_and_gradient", "adam_update", "grad_descent", "pixel_search",
 ]

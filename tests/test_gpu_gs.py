@@ -248,3 +248,28 @@ def test_kernel_timing_modes_count_executions_and_leave_results_alone():
         assert np.array_equal(a, b)
     with pytest.raises(RuntimeError):
         hg.hg_timing_begin(plan, hg.HG_KERNEL_GS_SLM, 0)
+
+
+def test_quantise_at_end_is_a_composition_of_calls():
+    """Quantise-at-end (continuous GS, then one quantisation of the final phase)
+    runs as two calls: hg_gs_iterate on a continuous plan for n iterations, then
+    zero iterations on an L-level plan, whose constrained start state is the
+    quantised phase and whose nmse[0] is that hologram's error."""
+    torch = torch_mod()
+    h, w, n, levels = 256, 256, 15, 4
+    t, phi = wl.target_and_phase(h, w, seed=31)
+    cont = make_plan(h, w, 0, True)
+    quant = make_plan(h, w, levels, True)
+    ph = dev(phi.copy())
+    hg.hg_gs_iterate(cont, dev(t), ph, n, cont.workspace())
+    lv = torch.zeros((h, w), dtype=torch.uint8, device="cuda")
+    nm = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hg.hg_gs_iterate(quant, dev(t), ph, 0, quant.workspace(), levels=lv, nmse=nm)
+    fres = dict(wavelength=532e-9, pitch=8e-6, distance=0.5)
+    ref_c = oracle.gs_iterate(t, phi, n, fresnel=fres)
+    ref_q = oracle.gs_iterate(t, ref_c["phase"], 0, levels=levels, fresnel=fres)
+    # the continuous phases agree to the continuous-phase bar (<= 1e-4 of the
+    # pixels off by more than 1e-3 rad), so levels may differ near boundaries
+    band = boundary_distance(ref_c["phase"], levels) < 1e-3
+    assert ((host(lv) != ref_q["levels"]) & ~band).mean() <= 1e-4
+    assert abs(host(nm)[0] - ref_q["nmse"][0]) <= 1e-3 * ref_q["nmse"][0]
