@@ -293,6 +293,41 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
             "pairs_nmse": float(nm.item())}
 
 
+def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
+    """Direct binary search on a 1024x1024 binary Fourier hologram (target of
+    the 1024^2 workload, random start and trial list from seed 12): trials/s.
+    Each trial is one pass over the replay field (rank-one update) plus a
+    one-workgroup decision."""
+    import numpy as np
+    w = wl.GS_FRESNEL_1024
+    t = torch.from_numpy(w.inputs()[0]).cuda()
+    plan = hg.Plan(w.width, w.height, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_BINARY_PHASE, 2)
+    rng = np.random.default_rng(12)
+    lev0 = torch.from_numpy(rng.integers(0, 2, (w.height, w.width)).astype(np.uint8)).cuda()
+    trials = torch.from_numpy(np.stack([rng.integers(0, w.height * w.width, n_trials),
+                                        rng.integers(0, 2, n_trials)], axis=1).astype(np.int32)).cuda()
+    ws = hg.search_workspace(plan)
+    acc = torch.empty(n_trials, dtype=torch.uint8, device="cuda")
+    nm = torch.empty(n_trials + 1, dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lev = lev0.clone()
+    hg.hg_pixel_search(plan, t, lev, trials[:50], ws, accepted=acc[:50], nmse=nm[:51], stream=stream)
+    lev = lev0.clone()
+    torch.cuda.synchronize()
+    a.record(stream)
+    hg.hg_pixel_search(plan, t, lev, trials, ws, accepted=acc, nmse=nm, stream=stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    rate = float(acc.float().mean().item())
+    npx = w.height * w.width
+    trial_bytes = npx * (8 + 4 + 8 * rate)
+    return {"workload": "dbs_fourier_binary_1024x1024", "trials": n_trials, "ms": round(ms, 2),
+            "trials_per_s": round(n_trials / (ms * 1e-3), 1), "us_per_trial": round(ms * 1e3 / n_trials, 2),
+            "accept_rate": round(rate, 4), "nmse_start": float(nm[0].item()), "nmse_end": float(nm[-1].item()),
+            "trial_pass_gbs": round(trial_bytes / (ms * 1e-3 / n_trials) / 1e9, 1)}
+
+
 def rocfft_reference(torch, stream, n: int = 1024, reps: int = 200) -> dict:
     """torch.fft (rocFFT) forward + inverse 2D transform of one n x n complex64
     field, back to back: a vendor-library reference point, not part of the path."""
@@ -419,6 +454,8 @@ def main() -> int:
         mix = batched_mix(hg, wl, torch, stream, mixed)
         log(f"  {mix}")
 
+    srch = pixel_search_1024(hg, wl, torch, stream)
+    log(f"pixel search: {srch}")
     osp = ospr_2048(hg, wl, torch, stream)
     log(f"OSPR 2048: {osp}")
     rf = rocfft_reference(torch, stream)
@@ -438,7 +475,8 @@ def main() -> int:
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
                       "target_seed": w.target_seed, "phase_seed": w.phase_seed},
            "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
-           "batched_mix": mix, "ospr": osp, "rocfft_reference": rf}
+           "batched_mix": mix, "ospr": osp, "pixel_search": srch,
+           "rocfft_reference": rf}
     print(json.dumps(out), flush=True)
     return 0
 

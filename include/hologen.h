@@ -166,6 +166,27 @@ hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase,
 hg_status hg_ospr_pairs(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_pairs,
                         uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
 
+/* Single-pixel search on a HG_PHASE_QUANTISED or HG_BINARY_PHASE plan
+ * (Sec. 7.3: direct binary search HoloGenAlgDSCuda, simulated annealing
+ * HoloGenAlgSACuda, single-pixel replay updates FFTUpdaterCuda).  The state
+ * is the level map `levels` [H][W] uint8 (in: start, out: result; values
+ * < L).  E = NMSE(|FFT2(Q1 exp(2 pi i l / L))|^2, ifftshift(target_amp)^2).
+ * Trial k (device array trials [n_trials][2] int32) moves pixel
+ * trials[k][0] = y W + x to level trials[k][1]; with dE the resulting change
+ * of E it is accepted iff dE < 0 (direct search, temperature == uniform ==
+ * NULL) or, annealing, iff dE < 0 or uniform[k] < exp(-dE / temperature[k])
+ * (device float arrays [n_trials], temperature > 0 in NMSE units).  The
+ * replay field is computed once per call and then updated in place by one
+ * pass per trial.  A trial whose pixel or level is out of range (or whose
+ * pixel holds a level >= L) is rejected without effect.
+ * accepted [n_trials] uint8 or NULL; nmse [n_trials + 1] float or NULL: E of
+ * the start state, then after each trial.
+ * workspace: hg_search_workspace_bytes(plan) bytes. */
+size_t hg_search_workspace_bytes(hg_plan plan);
+hg_status hg_pixel_search(hg_plan plan, const float* target_amp, uint8_t* levels, const int32_t* trials,
+                          int32_t n_trials, const float* temperature, const float* uniform, uint8_t* accepted,
+                          float* nmse, void* workspace, hipStream_t stream);
+
 /* Gradient-descent hologram optimisation: the method added beyond the
  * paper's library, whose further algorithms are left to future work (Sec. 8).
  * The parameter is the continuous SLM phase phi; each of the n_planes replay

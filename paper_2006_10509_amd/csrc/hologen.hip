@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -18,6 +19,7 @@
 
 #include "hologen.h"
 #include "reduce.hpp"
+#include "search.hpp"
 
 using namespace hg;
 
@@ -152,6 +154,8 @@ struct hg_plan_s {
   float2* inv_post_y = nullptr;
   float2* inv_post_x = nullptr;
   float2* lvl_tab = nullptr;
+  float2* unit_y = nullptr;  // exp(-2 pi i k / H), k < H: single-pixel replay updates
+  float2* unit_x = nullptr;  // exp(-2 pi i k / W), k < W
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
   int row_blocks = 0, col_blocks = 0;
   size_t ws_bytes = 0;     // workspace of one hologram (ws_layout(p, 1).total)
@@ -619,6 +623,15 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
       st = upload(p, to_f32(re, im), &p->lvl_tab);
     }
   }
+  for (int axis = 0; axis < 2 && st == HG_OK; ++axis) {
+    const int m = axis == 0 ? H : W;
+    std::vector<double> re(m), im(m);
+    for (int k = 0; k < m; ++k) {
+      re[k] = std::cos(2.0 * M_PI * k / m);
+      im[k] = -std::sin(2.0 * M_PI * k / m);
+    }
+    st = upload(p, to_f32(re, im), axis == 0 ? &p->unit_y : &p->unit_x);
+  }
   if (st != HG_OK) {
     free_plan(p);
     return st;
@@ -797,6 +810,105 @@ hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_pha
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials, (int)nb,
                        (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
   return launch_status("hg_ospr_pairs launch");
+}
+
+size_t hg_search_workspace_bytes(hg_plan plan) {
+  if (!plan) return 0;
+  const size_t n = npix(plan);
+  return align_up(n * sizeof(float2)) + 2 * align_up(n * sizeof(float)) + align_up(sizeof(Scalars)) +
+         align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double)) + align_up(SEARCH_MAX_BLOCKS * sizeof(double)) +
+         align_up(sizeof(SearchState));
+}
+
+hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, const int32_t* trials,
+                          int32_t n_trials, const float* temperature, const float* uniform, uint8_t* accepted,
+                          float* nmse, void* workspace, hipStream_t stream) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!p->lvl_tab || p->levels < 2)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_pixel_search needs a HG_PHASE_QUANTISED or HG_BINARY_PHASE plan");
+  if (!target_amp || !levels) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp and levels are required");
+  if (n_trials < 0) return fail(HG_ERR_INVALID_ARGUMENT, "n_trials must be >= 0");
+  if (n_trials > 0 && !trials) return fail(HG_ERR_INVALID_ARGUMENT, "trials is NULL");
+  if ((temperature == nullptr) != (uniform == nullptr))
+    return fail(HG_ERR_INVALID_ARGUMENT, "temperature and uniform must both be given (annealing) or both be NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  const int W = p->desc.width, H = p->desc.height;
+  const size_t n = npix(p);
+  char* b = static_cast<char*>(workspace);
+  float2* replay = reinterpret_cast<float2*>(b);
+  size_t off = align_up(n * sizeof(float2));
+  float* t2 = reinterpret_cast<float*>(b + off);
+  off += align_up(n * sizeof(float));
+  float* phase = reinterpret_cast<float*>(b + off);
+  off += align_up(n * sizeof(float));
+  Scalars* sc = reinterpret_cast<Scalars*>(b + off);
+  off += align_up(sizeof(Scalars));
+  double* stats = reinterpret_cast<double*>(b + off);
+  off += align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
+  double* partials = reinterpret_cast<double*>(b + off);
+  off += align_up(SEARCH_MAX_BLOCKS * sizeof(double));
+  SearchState* state = reinterpret_cast<SearchState*>(b + off);
+
+  Workspace w{replay, sc, stats, nullptr, nullptr};
+  enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, sc, stream);
+  const unsigned gb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_search_target, dim3(gb), dim3(256), 0, stream, target_amp, t2, H, W);
+  hipLaunchKernelGGL(k_search_phase, dim3(gb), dim3(256), 0, stream, (const uint8_t*)levels, phase, n,
+                     (float)(2.0 * M_PI / p->levels));
+  // R = FFT2(Q1 H): the GS start pass (row transforms) and a forward column pass
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+  GsRowArgs ra{};
+  ra.field = replay;
+  ra.phase0 = phase;
+  ra.H = H;
+  if (p->desc.propagation == HG_FRESNEL) {
+    ra.q1y = p->q1y;
+    ra.q1x = p->q1x;
+  }
+  ra.slm.lvl_tab = p->lvl_tab;
+  ra.slm.levels = p->levels;
+  ra.slm.inv_delta = (float)((double)p->levels / (2.0 * M_PI));
+  ra.slm.inv_delta_f64 = (double)p->levels / (2.0 * M_PI);
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
+  hipLaunchKernelGGL(rk.gs_start, dim3(p->row_blocks), dim3(rk.threads), rk.lds, stream, ra);
+  PropColArgs ca{};
+  ca.io = replay;
+  ca.W = W;
+  ca.scale = 1.0f;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
+  hipLaunchKernelGGL(ck.prop_fwd, dim3(p->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+
+  SearchArgs sa{};
+  sa.replay = replay;
+  sa.t2 = t2;
+  sa.levels = levels;
+  sa.trials = trials;
+  sa.temperature = temperature;
+  sa.uniform = uniform;
+  sa.lvl_tab = p->lvl_tab;
+  sa.q1y = ra.q1y;
+  sa.q1x = ra.q1x;
+  sa.unit_y = p->unit_y;
+  sa.unit_x = p->unit_x;
+  sa.sc = sc;
+  sa.state = state;
+  sa.partials = partials;
+  sa.accepted = accepted;
+  sa.nmse = nmse;
+  sa.H = H;
+  sa.W = W;
+  sa.L = p->levels;
+  const int nb = (int)std::min<size_t>((n + SEARCH_THREADS * 4 - 1) / (SEARCH_THREADS * 4), SEARCH_MAX_BLOCKS);
+  hipLaunchKernelGGL(k_search_error, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa);
+  hipLaunchKernelGGL(k_search_start, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, nb);
+  for (int k = 0; k < n_trials; ++k) {
+    hipLaunchKernelGGL(k_search_trial, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa, k);
+    hipLaunchKernelGGL(k_search_decide, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, k, nb);
+  }
+  return launch_status("hg_pixel_search launch");
 }
 
 size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes) {

@@ -40,7 +40,8 @@ HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
             "hg_propagate", "hg_gs_iterate", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
-            "hg_ospr", "hg_ospr_pairs", "hg_grad_workspace_bytes", "hg_grad",
+            "hg_ospr", "hg_ospr_pairs", "hg_search_workspace_bytes", "hg_pixel_search",
+            "hg_grad_workspace_bytes", "hg_grad",
             "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
 
 
@@ -96,6 +97,10 @@ def library() -> ctypes.CDLL:
     lib.hg_ospr.restype = i32
     lib.hg_ospr_pairs.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr_pairs.restype = i32
+    lib.hg_search_workspace_bytes.argtypes = [vp]
+    lib.hg_search_workspace_bytes.restype = sz
+    lib.hg_pixel_search.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hg_pixel_search.restype = i32
     lib.hg_grad_workspace_bytes.argtypes = [vp, i32]
     lib.hg_grad_workspace_bytes.restype = sz
     lib.hg_grad.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp]
@@ -255,6 +260,29 @@ def hg_ospr_pairs(plan: Plan, target_amp, sub_phase, intensity, workspace, holog
         _ptr(intensity, torch.float32, shape, "intensity"),
         _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
         _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
+
+
+def search_workspace(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty(int(library().hg_search_workspace_bytes(plan.handle)), dtype=torch.uint8, device=device)
+
+
+def hg_pixel_search(plan: Plan, target_amp, levels, trials, workspace, temperature=None, uniform=None,
+                    accepted=None, nmse=None, stream=None) -> None:
+    """Direct binary search (temperature None) or simulated annealing over the
+    [n, 2] int32 trial list (pixel index, candidate level); ``levels`` is
+    updated in place."""
+    import torch
+    shape = (plan.height, plan.width)
+    n = int(trials.shape[0])
+    _check(library().hg_pixel_search(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(levels, torch.uint8, shape, "levels"), _ptr(trials, torch.int32, (n, 2), "trials"), n,
+        _ptr(temperature, torch.float32, (n,), "temperature", optional=True),
+        _ptr(uniform, torch.float32, (n,), "uniform", optional=True),
+        _ptr(accepted, torch.uint8, (n,), "accepted", optional=True),
+        _ptr(nmse, torch.float32, (n + 1,), "nmse", optional=True),
+        _workspace(workspace, int(library().hg_search_workspace_bytes(plan.handle))), _stream(stream)))
 
 
 def workspace_bytes_batched(plan: Plan, batch: int) -> int:

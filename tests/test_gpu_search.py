@@ -1,0 +1,127 @@
+"""GPU single-pixel search (hg_pixel_search: direct binary search, simulated
+annealing, rank-one replay updates) against the oracle (oracle/search.py),
+which recomputes the replay field from scratch for every trial.
+
+Bars: the accept/reject decisions are identical up to the first trial whose
+error change lies within 1e-5 of the current NMSE of zero (a tie: the GPU
+sums the change in FP32 terms, so the decision may go either way there;
+after it the trajectories may legitimately differ); the NMSE of every state
+up to that point within 1e-4 relative.  At full size: direct search never
+raises the error, levels change only where trials were accepted, and the
+tracked NMSE equals that of the final level map computed from scratch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_10509_amd import hologen as hg
+from paper_2006_10509_amd import workloads as wl
+from gpu_util import dev, host, torch_mod
+
+pytestmark = pytest.mark.gpu
+FRESNEL = dict(wavelength=532e-9, pitch=8e-6, distance=0.5)
+
+
+def plan_for(h, w, levels, fresnel):
+    mod = hg.HG_BINARY_PHASE if levels == 2 else hg.HG_PHASE_QUANTISED
+    if fresnel:
+        return hg.Plan(w, h, hg.HG_FRESNEL, 532e-9, 8e-6, 0.5, mod, levels)
+    return hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, mod, levels)
+
+
+def run_search(plan, t, lev0, trials, temperature=None, uniform=None):
+    torch = torch_mod()
+    n = len(trials)
+    lv = dev(lev0.astype(np.uint8))
+    acc = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    nm = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    hg.hg_pixel_search(plan, dev(t), lv, dev(np.asarray(trials, dtype=np.int32).reshape(n, 2)),
+                       hg.search_workspace(plan),
+                       temperature=None if temperature is None else dev(np.asarray(temperature, np.float32)),
+                       uniform=None if uniform is None else dev(np.asarray(uniform, np.float32)),
+                       accepted=acc, nmse=nm)
+    return host(lv), host(acc).astype(bool), host(nm)
+
+
+def compare(gpu, ref):
+    """Index of the first tie (None if none); asserts agreement before it."""
+    _, acc, nm = gpu
+    for k in range(len(ref["accepted"])):
+        if abs(ref["dE"][k]) < 1e-5 * ref["nmse"][k]:
+            return k
+        assert acc[k] == ref["accepted"][k], k
+        assert abs(nm[k + 1] - ref["nmse"][k + 1]) <= 1e-4 * ref["nmse"][k + 1], k
+    return None
+
+
+def make_trials(h, w, levels, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, h * w, n), rng.integers(0, levels, n)], axis=1), rng
+
+
+@pytest.mark.parametrize("h,w,levels,fresnel,n", [
+    (32, 32, 2, False, 400),
+    (24, 60, 4, True, 300),
+    (64, 64, 8, True, 200),
+])
+def test_direct_search_matches_oracle(h, w, levels, fresnel, n):
+    print(f"search {h}x{w} L={levels} fresnel={fresnel} trials={n}", flush=True)
+    plan = plan_for(h, w, levels, fresnel)
+    t = wl.target_amplitude(h, w, seed=h * w + levels)
+    trials, rng = make_trials(h, w, levels, n, 5)
+    lev0 = rng.integers(0, levels, (h, w))
+    gpu = run_search(plan, t, lev0, trials)
+    ref = oracle.pixel_search(t, lev0, levels, [tuple(x) for x in trials], fresnel=FRESNEL if fresnel else None)
+    tie = compare(gpu, ref)
+    if tie is None:
+        assert np.array_equal(gpu[0], ref["levels"])
+    assert gpu[1].any()
+    assert np.all(np.diff(gpu[2]) <= 0)
+
+
+def test_annealing_matches_oracle():
+    h, w, levels, n = 32, 32, 4, 300
+    plan = plan_for(h, w, levels, False)
+    t = wl.target_amplitude(h, w, seed=9)
+    trials, rng = make_trials(h, w, levels, n, 6)
+    lev0 = rng.integers(0, levels, (h, w))
+    temp = 1e-3 * 0.98 ** np.arange(n)
+    u = rng.uniform(0, 1, n)
+    gpu = run_search(plan, t, lev0, trials, temp, u)
+    ref = oracle.pixel_search(t, lev0, levels, [tuple(x) for x in trials],
+                              temperature=temp.astype(np.float32).astype(np.float64),
+                              uniform=u.astype(np.float32).astype(np.float64))
+    tie = compare(gpu, ref)
+    if tie is None:
+        assert np.array_equal(gpu[0], ref["levels"])
+    assert (np.diff(ref["nmse"]) > 0).any()      # annealing took uphill moves
+
+
+def test_out_of_range_trials_are_rejected_no_ops():
+    h, w, levels = 32, 32, 2
+    plan = plan_for(h, w, levels, False)
+    t = wl.target_amplitude(h, w, seed=2)
+    lev0 = np.random.default_rng(1).integers(0, 2, (h, w))
+    trials = [(-1, 1), (h * w, 0), (5, 2), (7, -1), (3, 1 - int(lev0.ravel()[3]))]
+    lev, acc, nm = run_search(plan, t, lev0, trials)
+    assert not acc[:4].any()
+    changed = lev != lev0
+    assert changed.sum() == int(acc[4]) and (not acc[4] or changed.ravel()[3])
+    assert nm[1] == nm[0] and nm[4] == nm[0]
+
+
+def test_full_size_direct_search_properties():
+    h, w, levels, n = 1024, 1024, 2, 200
+    plan = plan_for(h, w, levels, False)
+    t = wl.target_amplitude(h, w, seed=2)
+    trials, rng = make_trials(h, w, levels, n, 7)
+    lev0 = rng.integers(0, levels, (h, w))
+    lev, acc, nm = run_search(plan, t, lev0, trials)
+    assert np.all(np.diff(nm) <= 0) and acc.any()
+    changed = np.flatnonzero((lev != lev0).ravel())
+    assert set(changed.tolist()) <= set(trials[acc, 0].tolist())
+    # NMSE of the final map from scratch: zero GS iterations on its phase
+    torch = torch_mod()
+    phase = dev((lev * (2 * np.pi / levels)).astype(np.float32))
+    e = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hg.hg_gs_iterate(plan, dev(t), phase, 0, plan.workspace(), nmse=e)
+    assert abs(host(e)[0] - nm[-1]) <= 1e-4 * nm[-1]
