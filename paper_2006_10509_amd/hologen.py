@@ -243,7 +243,7 @@ def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
         _ptr(phase, torch.float32, shape, "phase"),
         _ptr(levels, torch.uint8, shape, "levels", optional=True),
         _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
-        int(iterations), _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+        int(iterations), _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
 
 
 def hg_ospr_pairs(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=None,
@@ -315,7 +315,7 @@ def hg_ospr(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=N
         _ptr(holograms, torch.uint8, (n_sub,) + shape, "holograms", optional=True),
         _ptr(intensity, torch.float32, shape, "intensity"),
         _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
-        _ptr(workspace, torch.uint8, None, "workspace"), _stream(stream)))
+        _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
 
 
 def _workspace(ws, need: int, name: str = "workspace") -> int:
