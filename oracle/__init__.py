@@ -23,7 +23,8 @@ step by step in the order the method performs it:
                   replacement.
   metrics.py      energy-normalised NMSE of an intensity against a target.
   gs.py           Gerchberg-Saxton error-reduction iteration (Gerchberg &
-                  Saxton 1972; Fienup 1982).
+                  Saxton 1972; Fienup 1982), and its plane-by-plane
+                  multi-plane form.
   ospr.py         One-Step Phase-Retrieval (Cable, Buckley et al. 2004).
   grad.py         gradient-descent hologram optimisation: multi-plane NMSE
                   loss, its Wirtinger gradient and Adam (Kingma & Ba 2015).
@@ -39,7 +40,7 @@ from .optics import fresnel_chirp, fresnel_geometry, propagate
 from .constraints import (quantise_level, quantise_phase_level, phase_only,
                           replace_amplitude, binarise)
 from .metrics import nmse
-from .gs import gs_iterate
+from .gs import gs_iterate, gs_multiplane
 from .ospr import ospr, ospr_pairs
 from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
 from .search import pixel_search
@@ -48,6 +49,6 @@ __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
     "fresnel_chirp", "fresnel_geometry", "propagate",
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
-    "binarise", "nmse", "gs_iterate", "ospr", "ospr_pairs",
+    "binarise", "nmse", "gs_iterate", "gs_multiplane", "ospr", "ospr_pairs",
     "source_chirp", "loss_and_gradient", "adam_update", "grad_descent", "pixel_search",
 ]

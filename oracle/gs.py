@@ -115,3 +115,56 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
     if trace and levels:
         out["trace"] = states
     return out
+
+
+def gs_multiplane(target_amps, phi0: np.ndarray, iterations: int, planes, levels: int = 0,
+                  illumination: Optional[np.ndarray] = None) -> dict:
+    """Multi-plane GS, one plane after another.
+
+    Each iteration runs one GS step per replay plane j = 0..P-1 on the same
+    SLM state (plane j: Fresnel dict, or None for a Fourier plane):
+
+      R_j = FFT2(Q1_j H);  record NMSE(|R_j|^2, T_j^2)
+      H   = A P(conj(Q1_j) IFFT2(T_j R_j / |R_j|))
+
+    nmse holds the error of every step (iterations * P values, plane j of
+    iteration k at k * P + j), then the error of the final state at every
+    plane (P values).  With one plane this is gs_iterate.
+    """
+    t_f = [ifftshift(np.asarray(t, dtype=np.float64)) for t in target_amps]
+    h, w = t_f[0].shape
+    amp = np.ones((h, w)) if illumination is None else np.asarray(illumination, np.float64)
+    q1 = []
+    for p in planes:
+        if p is None:
+            q1.append(np.ones((h, w), dtype=np.complex128))
+        else:
+            q1.append(np.outer(fresnel_chirp(h, p["pitch"], p["wavelength"], p["distance"]),
+                               fresnel_chirp(w, p["pitch"], p["wavelength"], p["distance"])))
+    phi0 = np.asarray(phi0, dtype=np.float64)
+    if levels:
+        lev = quantise_phase_level(phi0, levels)
+        unit = np.exp(1j * lev * (TWO_PI / levels))
+    else:
+        lev = None
+        unit = np.exp(1j * phi0)
+    slm = amp * unit
+    errors = []
+    for k in range(iterations):
+        for j in range(len(planes)):
+            replay = fft2(q1[j] * slm)
+            errors.append(nmse_fn(np.abs(replay) ** 2, t_f[j] ** 2))
+            back = np.conj(q1[j]) * ifft2(replace_amplitude(replay, t_f[j]))
+            if levels:
+                lev = quantise_level(back, levels)
+                unit = np.exp(1j * lev * (TWO_PI / levels))
+            else:
+                unit = phase_only(back)
+            slm = amp * unit
+    for j in range(len(planes)):
+        errors.append(nmse_fn(np.abs(fft2(q1[j] * slm)) ** 2, t_f[j] ** 2))
+    if levels:
+        phase = lev * (TWO_PI / levels)
+    else:
+        phase = np.mod(np.arctan2(unit.imag, unit.real), TWO_PI)
+    return {"phase": phase, "levels": lev, "nmse": errors}

@@ -160,3 +160,51 @@ def test_trace_matches_separate_runs():
         part = oracle.gs_iterate(t, phi, k, levels=8)
         assert np.array_equal(full["trace"][k]["levels"], part["levels"])
     assert np.array_equal(full["trace"][0]["angle"], phi)
+
+
+# ---------------------------------------------------------------------------
+# multi-plane GS, one plane after another
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("levels", [0, 4])
+def test_multiplane_with_one_plane_is_gs(levels):
+    t, phi = synthetic(24, 40, 13)
+    a = oracle.gs_multiplane([t], phi, 6, [FRESNEL], levels=levels)
+    b = oracle.gs_iterate(t, phi, 6, levels=levels, fresnel=FRESNEL)
+    assert a["nmse"] == b["nmse"]
+    assert np.array_equal(a["phase"], b["phase"])
+
+
+@pytest.mark.parametrize("levels", [0, 8])
+def test_multiplane_with_a_repeated_plane_is_gs_with_twice_the_iterations(levels):
+    t, phi = synthetic(32, 24, 14)
+    a = oracle.gs_multiplane([t, t], phi, 5, [FRESNEL, FRESNEL], levels=levels)
+    b = oracle.gs_iterate(t, phi, 10, levels=levels, fresnel=FRESNEL)
+    assert a["nmse"][:10] == b["nmse"][:10]
+    assert a["nmse"][10] == a["nmse"][11] == b["nmse"][10]
+    assert np.array_equal(a["phase"], b["phase"])
+
+
+def test_multiplane_consistent_targets_are_a_fixed_point():
+    h, w = 20, 24
+    rng = np.random.default_rng(15)
+    phi = rng.uniform(0, TWO_PI, (h, w))
+    planes = [FRESNEL, dict(FRESNEL, distance=0.4), None]
+    targets = []
+    for p in planes:
+        q1 = oracle.source_chirp(h, w, p)
+        targets.append(np.fft.fftshift(np.abs(np.fft.fft2(q1 * np.exp(1j * phi)))))
+    out = oracle.gs_multiplane(targets, phi, 3, planes)
+    assert max(out["nmse"]) <= 1e-24
+    assert np.abs(np.angle(np.exp(1j * (out["phase"] - phi)))).max() <= 1e-10
+
+
+def test_multiplane_final_errors_are_the_physical_ones():
+    h, w = 16, 20
+    t1, phi = synthetic(h, w, 16)
+    t2, _ = synthetic(h, w, 17)
+    planes = [FRESNEL, dict(FRESNEL, distance=0.45)]
+    out = oracle.gs_multiplane([t1, t2], phi, 4, planes, levels=8)
+    slm = np.exp(1j * out["phase"])
+    for j, (t, p) in enumerate(zip((t1, t2), planes)):
+        replay = oracle.propagate(slm, +1, fresnel=True, **p)
+        assert abs(out["nmse"][8 + j] - oracle.nmse(np.abs(replay) ** 2, t * t)) <= 1e-12
