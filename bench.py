@@ -154,7 +154,22 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
     b.synchronize()
     ms = a.elapsed_time(b)
     fin = losses[:, -1].cpu().numpy()
+    # the same problems with plane-by-plane multi-plane GS (continuous phase),
+    # 100 iterations of 3 steps each: summed final NMSE over the planes
+    mws = hg.multiplane_workspace(planes)
+    iters = 100
+    mnm = torch.empty((problems, iters * len(planes) + len(planes)), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    a.record(stream)
+    for bi, (tg, p0) in enumerate(data):
+        hg.hg_gs_multiplane(planes, tg, p0.clone(), iters, mws, nmse=mnm[bi], stream=stream)
+    b.record(stream)
+    b.synchronize()
+    mp_ms = a.elapsed_time(b)
+    mp_final = mnm[:, -len(planes):].sum(dim=1).cpu().numpy()
     return {"workload": w.name, "problems": problems, "steps": w.steps, "planes": len(w.distances),
+            "multiplane_gs": {"iterations": iters, "ms": round(mp_ms, 2),
+                              "final_loss_mean": float(mp_final.mean())},
             "ms": round(ms, 2), "problem_steps_per_s": round(problems * w.steps / (ms * 1e-3), 1),
             "ms_per_step": round(ms / (problems * w.steps), 4),
             "final_loss_mean": float(fin.mean()), "initial_loss_mean": float(losses[:, 0].mean().item())}

@@ -153,6 +153,22 @@ hg_status hg_gs_iterate_batched(hg_plan plan, int32_t batch, const float* target
 hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_sub,
                   uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
 
+/* Multi-plane Gerchberg-Saxton, one replay plane after another: each of the
+ * `iterations` iterations runs one GS step per plane j = 0..n_planes-1 on
+ * the same SLM state,
+ *   R_j = FFT2(Q1_j H);  H = A P(conj(Q1_j) IFFT2(T_j R_j / |R_j|)),
+ * with Q1_j the source chirp of plans[j] (1 for a HG_FOURIER plan) and P and
+ * the start constraint as in hg_gs_iterate.  All plans share width, height,
+ * modulation and levels.  target_amp [n_planes][H][W] centred; phase, levels
+ * and illumination as in hg_gs_iterate.  nmse [iterations * n_planes +
+ * n_planes] or NULL: the error of every step (plane j of iteration k at
+ * k n_planes + j), then of the final state at every plane.
+ * workspace: hg_multiplane_workspace_bytes(plans[0], n_planes) bytes. */
+size_t hg_multiplane_workspace_bytes(hg_plan plan, int32_t n_planes);
+hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float* target_amp,
+                            const float* illumination, float* phase, uint8_t* levels, float* nmse,
+                            int32_t iterations, void* workspace, hipStream_t stream);
+
 /* OSPR with real and imaginary subframe pairs, binary phase, on a HG_FOURIER
  * plan: one inverse transform per pair gives two subframes,
  *   G_n = IFFT2(ifftshift(target_amp exp(i sub_phase[n]))),

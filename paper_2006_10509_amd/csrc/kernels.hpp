@@ -375,6 +375,11 @@ struct GsRowArgs {
   uint8_t* levels_out;
   const float2* tw;
   const float2* twr;
+  // General pass only: when q_out_set, the SLM field leaves for the next
+  // replay plane through the chirp qo (null -> Fourier plane) instead of Q1.
+  int q_out_set;
+  const float2* qoy;
+  const float2* qox;
   uint32_t px;              // batch: pixels per hologram; item blockIdx.y is offset by blockIdx.y * px
   // Batch item blockIdx.y of a launch over a stack of same-shape holograms
   // (gridDim.y items; the illumination is shared).
@@ -536,6 +541,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
     });
   } else {
     const bool out = rt.live && (a.phase_out || a.levels_out);
+    const bool fres_out = a.q_out_set ? (a.qoy != nullptr) : fres;
+    const float2 qoy = a.q_out_set ? (fres_out ? a.qoy[rt.y] : make_float2(1.f, 0.f)) : qy;
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
       float2 q = make_float2(1.f, 0.f);
@@ -547,7 +554,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       float2 u = slm_constrain_rt(g, a.slm, level);
       if (out) write_state(a, row + x, u, level);
       if (a.illum) u = cscale(u, ldg(a.illum, row + x));
-      v[s] = fres ? cmul(u, q) : u;
+      if (a.q_out_set && fres_out) q = cmul(qoy, ldg(a.qox, (uint32_t)x));
+      v[s] = fres_out ? cmul(u, q) : u;
     });
   }
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);

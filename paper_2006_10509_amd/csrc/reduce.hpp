@@ -125,6 +125,19 @@ __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce(const float* __re
   if (threadIdx.x == 0) nmse[blockIdx.x] = (float)(s / sc->denom);
 }
 
+// nmse[b] = sum_wg partials[b][wg] / denom of plane (first + b) % planes: the
+// steps of a plane-by-plane multi-plane loop, one workgroup per step.
+__global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce_planes(const float* __restrict__ partials, int nwg,
+                                                                      const Scalars* __restrict__ sc, int planes,
+                                                                      int first, float* __restrict__ nmse) {
+  __shared__ double red[STATS_THREADS];
+  const float* p = partials + (size_t)blockIdx.x * nwg;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];
+  s = block_sum_f64<STATS_THREADS>(s, red);
+  if (threadIdx.x == 0) nmse[blockIdx.x] = (float)(s / sc[(first + (int)blockIdx.x) % planes].denom);
+}
+
 // loss[k] = sum_j (sum_wg partials[k][j][wg]) / denom_j: the summed NMSE of the
 // `planes` replay planes of state k, one workgroup per state, fixed order.
 __global__ __launch_bounds__(STATS_THREADS) void k_loss_reduce(const float* __restrict__ partials, int nwg,

@@ -40,6 +40,7 @@ HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
             "hg_propagate", "hg_gs_iterate", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
+            "hg_multiplane_workspace_bytes", "hg_gs_multiplane",
             "hg_ospr", "hg_ospr_pairs", "hg_search_workspace_bytes", "hg_pixel_search",
             "hg_grad_workspace_bytes", "hg_grad",
             "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
@@ -97,6 +98,10 @@ def library() -> ctypes.CDLL:
     lib.hg_ospr.restype = i32
     lib.hg_ospr_pairs.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hg_ospr_pairs.restype = i32
+    lib.hg_multiplane_workspace_bytes.argtypes = [vp, i32]
+    lib.hg_multiplane_workspace_bytes.restype = sz
+    lib.hg_gs_multiplane.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.hg_gs_multiplane.restype = i32
     lib.hg_search_workspace_bytes.argtypes = [vp]
     lib.hg_search_workspace_bytes.restype = sz
     lib.hg_pixel_search.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -260,6 +265,29 @@ def hg_ospr_pairs(plan: Plan, target_amp, sub_phase, intensity, workspace, holog
         _ptr(intensity, torch.float32, shape, "intensity"),
         _ptr(nmse, torch.float32, (1,), "nmse", optional=True),
         _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
+
+
+def multiplane_workspace(planes, device="cuda"):
+    import torch
+    planes, _ = _plans(planes)
+    n = int(library().hg_multiplane_workspace_bytes(planes[0].handle, len(planes)))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def hg_gs_multiplane(planes, target_amp, phase, iterations: int, workspace, illumination=None, levels=None,
+                     nmse=None, stream=None) -> None:
+    """Multi-plane GS, one plane after another; target_amp is [n_planes, H, W]."""
+    import torch
+    planes, arr = _plans(planes)
+    P = len(planes)
+    shape = (planes[0].height, planes[0].width)
+    need = int(library().hg_multiplane_workspace_bytes(planes[0].handle, P))
+    _check(library().hg_gs_multiplane(
+        arr, P, _ptr(target_amp, torch.float32, (P,) + shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape, "illumination", optional=True),
+        _ptr(phase, torch.float32, shape, "phase"), _ptr(levels, torch.uint8, shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (iterations * P + P,), "nmse", optional=True), int(iterations),
+        _workspace(workspace, need), _stream(stream)))
 
 
 def search_workspace(plan: Plan, device="cuda"):

@@ -273,3 +273,44 @@ def test_quantise_at_end_is_a_composition_of_calls():
     band = boundary_distance(ref_c["phase"], levels) < 1e-3
     assert ((host(lv) != ref_q["levels"]) & ~band).mean() <= 1e-4
     assert abs(host(nm)[0] - ref_q["nmse"][0]) <= 1e-3 * ref_q["nmse"][0]
+
+
+# ---------------------------------------------------------------------------
+# multi-plane GS (hg_gs_multiplane)
+# ---------------------------------------------------------------------------
+def run_multiplane(planes, targets, phi0, iters, want_levels=True):
+    torch = torch_mod()
+    P = len(planes)
+    h, w = phi0.shape
+    ph = dev(phi0.copy())
+    lv = torch.zeros((h, w), dtype=torch.uint8, device="cuda") if want_levels else None
+    nm = torch.zeros(iters * P + P, dtype=torch.float32, device="cuda")
+    hg.hg_gs_multiplane(planes, dev(targets), ph, iters, hg.multiplane_workspace(planes), levels=lv, nmse=nm)
+    return host(ph), None if lv is None else host(lv), host(nm)
+
+
+def test_multiplane_one_plane_and_repeated_plane_are_gs_bitwise():
+    h, w, levels = 256, 256, 8
+    t, phi = wl.target_and_phase(h, w, seed=23)
+    plan = make_plan(h, w, levels, True)
+    gs_ph, gs_lv, gs_nm = run_gs(plan, t, phi, 6)
+    ph, lv, nm = run_multiplane([plan], t[None], phi, 6)
+    assert np.array_equal(ph, gs_ph) and np.array_equal(lv, gs_lv)
+    assert np.array_equal(nm[:6], gs_nm[:6]) and abs(nm[6] - gs_nm[6]) <= 1e-6 * gs_nm[6]
+    gs2 = run_gs(plan, t, phi, 8)
+    ph2, lv2, nm2 = run_multiplane([plan, plan], np.stack([t, t]), phi, 4)
+    assert np.array_equal(ph2, gs2[0]) and np.array_equal(nm2[:8], gs2[2][:8])
+
+
+def test_multiplane_three_planes_match_oracle():
+    h, w = 256, 256
+    zs = (0.40, 0.45, 0.50)
+    planes = [hg.Plan(w, h, hg.HG_FRESNEL, 532e-9, 8e-6, z) for z in zs]
+    targets = np.stack([wl.target_amplitude(h, w, seed=50 + j) for j in range(3)])
+    phi = wl.uniform_phase(h, w, seed=53)
+    ph, _, nm = run_multiplane(planes, targets, phi, 5, want_levels=False)
+    ref = oracle.gs_multiplane(list(targets), phi, 5, [dict(wavelength=532e-9, pitch=8e-6, distance=z) for z in zs])
+    rel = np.abs(nm - np.array(ref["nmse"])) / np.array(ref["nmse"])
+    assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
+    l2, frac = phase_parity(ph, ref["phase"])
+    assert l2 <= 1e-4 and frac <= 1e-4, (l2, frac)
