@@ -16,8 +16,8 @@ step by step in the order the method performs it:
   dft.py          discrete Fourier transform: a naive O(N^2) DFT and the
                   oracle's own recursive mixed-radix Cooley-Tukey FFT
                   (Cooley & Tukey 1965), 2D as rows then columns.
-  optics.py       Fourier and single-FFT Fresnel propagation (Goodman,
-                  Introduction to Fourier Optics, Fresnel diffraction).
+  optics.py       Fourier, single-FFT Fresnel and angular-spectrum
+                  propagation (Goodman, Introduction to Fourier Optics).
   constraints.py  SLM-plane phase-only projection, uniform L-level phase
                   quantiser, binary-phase binariser, replay-plane amplitude
                   replacement.
@@ -36,7 +36,8 @@ function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 brute-force sums, invariants and independent library routines.
 """
 from .dft import dft_naive, fft, ifft, fft2, ifft2, fftshift, ifftshift
-from .optics import fresnel_chirp, fresnel_geometry, propagate
+from .optics import (fresnel_chirp, fresnel_geometry, propagate, spatial_frequencies,
+                     angular_transfer, angular_spectrum)
 from .constraints import (quantise_level, quantise_phase_level, phase_only,
                           replace_amplitude, binarise)
 from .metrics import nmse
@@ -47,7 +48,8 @@ from .search import pixel_search
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
-    "fresnel_chirp", "fresnel_geometry", "propagate",
+    "fresnel_chirp", "fresnel_geometry", "propagate", "spatial_frequencies", "angular_transfer",
+    "angular_spectrum",
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
     "binarise", "nmse", "gs_iterate", "gs_multiplane", "ospr", "ospr_pairs",
     "source_chirp", "loss_and_gradient", "adam_update", "grad_descent", "pixel_search",

@@ -36,7 +36,7 @@ from typing import Optional
 import numpy as np
 
 from .dft import fft2, ifft2, ifftshift
-from .optics import fresnel_chirp
+from .optics import fresnel_chirp, angular_spectrum
 from .constraints import quantise_level, quantise_phase_level, phase_only, replace_amplitude
 from .metrics import nmse as nmse_fn
 
@@ -46,7 +46,8 @@ TWO_PI = 2.0 * np.pi
 def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
                levels: int = 0, illumination: Optional[np.ndarray] = None,
                fresnel: Optional[dict] = None, fienup: bool = False,
-               return_back: bool = False, trace: bool = False) -> dict:
+               return_back: bool = False, trace: bool = False,
+               angular: Optional[dict] = None) -> dict:
     """Run GS from phi0.
 
     target_amp, phi0: [H][W] real arrays (target in centred order, phase in SLM
@@ -59,10 +60,13 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
     decision was to a level boundary.  trace (quantised mode) adds, for every
     state k = 0..n, the levels of H_k and the angle that was quantised to get
     them (phi_0 for k = 0, arg G_{k-1} after that).
+    angular: instead of fresnel, a dict (wavelength, pitch, distance) for the
+    angular-spectrum model: R_k = AS_z(H_k) and G_k = AS_-z(R'_k) on the SLM's
+    own grid, with the target in its centred (natural) order, no shift.
     """
     t_amp = np.asarray(target_amp, dtype=np.float64)
     h, w = t_amp.shape
-    t_f = ifftshift(t_amp)
+    t_f = t_amp if angular else ifftshift(t_amp)
     t_int = t_f * t_f
     amp = np.ones((h, w)) if illumination is None else np.asarray(illumination, np.float64)
     if fresnel is None:
@@ -83,17 +87,25 @@ def gs_iterate(target_amp: np.ndarray, phi0: np.ndarray, iterations: int,
     if trace and levels:
         states.append({"levels": lev.astype(np.uint8), "angle": phi0.copy()})
 
-    c_scale = np.sqrt(h * w * np.sum(amp * amp) / np.sum(t_f * t_f))
+    # |R|^2 sums to N_px sum A^2 through the unnormalised FFT, to sum A^2 through
+    # the (unitary) angular-spectrum operator
+    c_scale = np.sqrt((1 if angular else h * w) * np.sum(amp * amp) / np.sum(t_f * t_f))
     errors, fienup_err = [], []
     back = None
+    if angular:
+        forward = lambda f: angular_spectrum(f, +1, angular["wavelength"], angular["pitch"], angular["distance"])
+        backward = lambda f: angular_spectrum(f, -1, angular["wavelength"], angular["pitch"], angular["distance"])
+    else:
+        forward = lambda f: fft2(q1 * f)
+        backward = lambda f: np.conj(q1) * ifft2(f)
     for k in range(iterations + 1):
-        replay = fft2(q1 * slm)
+        replay = forward(slm)
         errors.append(nmse_fn(np.abs(replay) ** 2, t_int))
         if fienup:
             fienup_err.append(float(np.sum((np.abs(replay) - c_scale * t_f) ** 2)))
         if k == iterations:
             break
-        back = np.conj(q1) * ifft2(replace_amplitude(replay, t_f))
+        back = backward(replace_amplitude(replay, t_f))
         if levels:
             lev = quantise_level(back, levels)
             unit = np.exp(1j * lev * (TWO_PI / levels))

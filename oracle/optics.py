@@ -24,6 +24,17 @@ and the backward operator is its exact algebraic inverse
   U_0 = conj(Q1) * fftshift(IFFT2(ifftshift(conj(Q2) * U_z / c))).
 
 Both planes are stored in centred image order (optical axis at (H//2, W//2)).
+
+Angular spectrum (Goodman, propagation of the angular spectrum): the field at
+distance z on the same grid (pitch p) is
+
+  U_z = IFFT2(FFT2(U_0) * exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)))
+
+with fx = kx / (W p) for the FFT index kx (kx - W from kx >= (W + 1) // 2 on),
+fy likewise, and zero transfer where the root is imaginary (evanescent
+waves).  Backward propagation uses the conjugate transfer function.  Both
+planes keep the natural array order (the optical axis at (H//2, W//2) of a
+centred image stays there).
 """
 from __future__ import annotations
 
@@ -68,3 +79,32 @@ def propagate(u: np.ndarray, direction: int, fresnel: bool = False,
     if direction == 1:
         return g["prefactor"] * g["q2"] * fftshift(fft2(ifftshift(g["q1"] * u)))
     return np.conj(g["q1"]) * fftshift(ifft2(ifftshift(np.conj(g["q2"]) * u / g["prefactor"])))
+
+
+def spatial_frequencies(n: int, pitch: float) -> np.ndarray:
+    """Frequency (1/m) of FFT index k of an n-point axis with sample pitch p."""
+    k = np.arange(n, dtype=np.float64)
+    k = np.where(k < (n + 1) // 2, k, k - n)
+    return k / (n * pitch)
+
+
+def angular_transfer(h: int, w: int, wavelength: float, pitch: float, distance: float) -> np.ndarray:
+    """exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) in FFT order; 0 where evanescent."""
+    fy = spatial_frequencies(h, pitch)[:, None]
+    fx = spatial_frequencies(w, pitch)[None, :]
+    arg = 1.0 / (wavelength * wavelength) - fx * fx - fy * fy
+    root = np.sqrt(np.maximum(arg, 0.0))
+    return np.where(arg > 0.0, np.exp(2j * np.pi * distance * root), 0.0)
+
+
+def angular_spectrum(u: np.ndarray, direction: int, wavelength: float, pitch: float,
+                     distance: float) -> np.ndarray:
+    """Angular-spectrum propagation over `distance` (direction +1) or back (-1)."""
+    u = np.asarray(u, dtype=np.complex128)
+    if direction not in (1, -1):
+        raise ValueError("direction must be +1 or -1")
+    h, w = u.shape[-2:]
+    tf = angular_transfer(h, w, wavelength, pitch, distance)
+    if direction == -1:
+        tf = np.conj(tf)
+    return ifft2(fft2(u) * tf)

@@ -208,3 +208,25 @@ def test_multiplane_final_errors_are_the_physical_ones():
     for j, (t, p) in enumerate(zip((t1, t2), planes)):
         replay = oracle.propagate(slm, +1, fresnel=True, **p)
         assert abs(out["nmse"][8 + j] - oracle.nmse(np.abs(replay) ** 2, t * t)) <= 1e-12
+
+
+ANGULAR = dict(wavelength=532e-9, pitch=8e-6, distance=0.05)
+
+
+@pytest.mark.parametrize("levels", [0, 8])
+def test_angular_spectrum_gs_fienup_error_never_increases(levels):
+    t, phi = synthetic(40, 48, 18)
+    out = oracle.gs_iterate(t, phi, 20, levels=levels, angular=ANGULAR, fienup=True)
+    e = np.array(out["fienup"])
+    assert np.all(e[1:] <= e[:-1] * (1 + 1e-12)), e
+    assert e[-1] < e[0]
+
+
+def test_angular_spectrum_gs_consistent_target_is_a_fixed_point():
+    h, w = 24, 32
+    rng = np.random.default_rng(19)
+    phi = rng.uniform(0, TWO_PI, (h, w))
+    t = np.abs(oracle.angular_spectrum(np.exp(1j * phi), +1, **ANGULAR))   # natural order, no shift
+    out = oracle.gs_iterate(t, phi, 3, angular=ANGULAR)
+    assert max(out["nmse"]) <= 1e-24
+    assert np.abs(np.angle(np.exp(1j * (out["phase"] - phi)))).max() <= 1e-10

@@ -107,3 +107,65 @@ def test_fourier_mode_is_raw_transform_pair():
     y = oracle.propagate(x, +1)
     assert np.linalg.norm(y - np.fft.fft2(x)) <= 1e-13 * np.linalg.norm(y)
     assert np.linalg.norm(oracle.propagate(y, -1) - x) <= 1e-13 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------------------
+# angular spectrum
+# ---------------------------------------------------------------------------
+AS = dict(wavelength=532e-9, pitch=8e-6)
+
+
+def _field(h, w, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(h, w)) + 1j * rng.normal(size=(h, w))
+
+
+def test_angular_spectrum_zero_distance_is_identity():
+    u = _field(24, 40, 1)
+    assert np.allclose(oracle.angular_spectrum(u, +1, distance=0.0, **AS), u, rtol=0, atol=1e-12)
+
+
+def test_angular_spectrum_semigroup_and_inverse():
+    u = _field(32, 48, 2)
+    a = oracle.angular_spectrum(oracle.angular_spectrum(u, +1, distance=0.03, **AS), +1, distance=0.05, **AS)
+    b = oracle.angular_spectrum(u, +1, distance=0.08, **AS)
+    assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
+    back = oracle.angular_spectrum(b, -1, distance=0.08, **AS)
+    assert np.abs(back - u).max() <= 1e-10 * np.abs(u).max()
+
+
+def test_angular_spectrum_plane_wave_closed_form():
+    h, w, ky, kx, z = 30, 40, 3, -7, 0.11
+    yy, xx = np.mgrid[0:h, 0:w]
+    u = np.exp(2j * np.pi * (kx * xx / w + ky * yy / h))
+    fx, fy = kx / (w * AS["pitch"]), ky / (h * AS["pitch"])
+    kz = 2 * np.pi * z * np.sqrt(1 / AS["wavelength"] ** 2 - fx ** 2 - fy ** 2)
+    expect = u * np.exp(1j * kz)
+    got = oracle.angular_spectrum(u, +1, distance=z, **AS)
+    assert np.abs(got - expect).max() <= 1e-9
+
+
+def test_angular_spectrum_frequencies_follow_fft_order():
+    f = oracle.spatial_frequencies(6, 2.0)
+    assert np.allclose(f, np.fft.fftfreq(6, 2.0), rtol=0, atol=0)
+    f = oracle.spatial_frequencies(5, 0.5)
+    assert np.allclose(f, np.fft.fftfreq(5, 0.5), rtol=0, atol=1e-15)
+
+
+def test_angular_spectrum_gaussian_beam():
+    """A paraxial Gaussian beam (waist 10 px) propagated 2 cm: the closed form,
+    including exp(i k z), to the sampling accuracy."""
+    h = w = 128
+    p, lam, w0, z = AS["pitch"], AS["wavelength"], 80e-6, 0.02
+    y = (np.arange(h) - h // 2) * p
+    x = (np.arange(w) - w // 2) * p
+    r2 = y[:, None] ** 2 + x[None, :] ** 2
+    u0 = np.exp(-r2 / w0 ** 2)
+    zr = np.pi * w0 ** 2 / lam
+    wz = w0 * np.sqrt(1 + (z / zr) ** 2)
+    inv_r = z / (z ** 2 + zr ** 2)
+    k = 2 * np.pi / lam
+    kz = 2 * np.pi * np.mod(z / lam, 1.0)
+    expect = (w0 / wz) * np.exp(-r2 / wz ** 2) * np.exp(1j * (kz - np.arctan(z / zr) + 0.5 * k * r2 * inv_r))
+    got = oracle.angular_spectrum(u0, +1, distance=z, **AS)
+    assert np.linalg.norm(got - expect) <= 1e-6 * np.linalg.norm(expect)
