@@ -55,17 +55,20 @@ typedef enum {
   HG_ERR_INTERNAL = 5
 } hg_status;
 
-enum { HG_FOURIER = 0, HG_FRESNEL = 1 };                               /* propagation */
+enum { HG_FOURIER = 0, HG_FRESNEL = 1, HG_ANGULAR = 2 };                               /* propagation */
 enum { HG_PHASE = 0, HG_PHASE_QUANTISED = 1, HG_BINARY_PHASE = 2 };   /* SLM modulation */
 enum { HG_FORWARD = 1 /* SLM -> replay */, HG_INVERSE = -1 /* replay -> SLM */ };
 
 typedef struct {
   int32_t width, height;   /* SLM resolution in pixels; each must be a compiled
                               transform length (hg_length_supported)            */
-  int32_t propagation;     /* HG_FOURIER or HG_FRESNEL                           */
-  double wavelength;       /* metres; Fresnel only: finite and > 0               */
-  double pixel_pitch;      /* metres; Fresnel only: finite and > 0               */
-  double distance;         /* metres; Fresnel only: finite and > 0               */
+  int32_t propagation;     /* HG_FOURIER, HG_FRESNEL or HG_ANGULAR               */
+  double wavelength;       /* metres; Fresnel, angular: finite and > 0           */
+  double pixel_pitch;      /* metres; Fresnel, angular: finite and > 0; angular
+                              also needs pixel_pitch > wavelength / sqrt(2), so
+                              that no sampled plane wave is evanescent          */
+  double distance;         /* metres; Fresnel: finite and > 0; angular: finite
+                              (negative propagates backwards)                   */
   int32_t modulation;      /* HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE    */
   int32_t levels;          /* 0 for HG_PHASE; 2..256 for HG_PHASE_QUANTISED;
                               2 for HG_BINARY_PHASE                              */
@@ -97,6 +100,12 @@ int32_t hg_length_supported(int32_t n);
  *       Q2 = exp(i pi (x^2 + y^2)/(lambda z)) at x = (k - W/2) lambda z/(W p),
  *       c  = exp(i 2 pi z / lambda) / (i lambda z) * p^2;
  *     SLM field in natural order, replay field in centred order.
+ *   HG_ANGULAR: angular-spectrum propagation on the SLM's own grid (the
+ *     near-field model that complements Sec. 3's Fresnel and Fraunhofer
+ *     transforms):
+ *       U_z = IFFT2(FFT2(U_0) T),  T = exp(i 2 pi z sqrt(1/lambda^2 - fx^2 - fy^2))
+ *     at fx = kx / (W p) for FFT index kx (kx - W from kx >= (W + 1) / 2 on),
+ *     fy likewise; the inverse uses conj(T).  Both planes in natural order.
  * in and out may be the same buffer.  workspace may be NULL (unused). */
 hg_status hg_propagate(hg_plan plan, const void* in_c64, void* out_c64, int32_t direction,
                        void* workspace, hipStream_t stream);
@@ -108,6 +117,9 @@ hg_status hg_propagate(hg_plan plan, const void* in_c64, void* out_c64, int32_t 
  *                                    above for HG_FRESNEL)
  *     nmse[k] = NMSE(|R_k|^2, T_f^2); stop at k = iterations
  *     H_{k+1} = A P(conj(Q1) IFFT2(T_f R_k / |R_k|))
+ * For a HG_ANGULAR plan R_k = AS_z(H_k), H_{k+1} = A P(AS_-z(T_f R_k / |R_k|))
+ * with the angular-spectrum operator of hg_propagate and T_f = target_amp
+ * (no shift: the replay plane keeps the SLM's natural order).
  * with P = phase-only projection G/|G| (HG_PHASE) or the uniform quantiser
  * l = floor(mod(arg G, 2 pi) L / (2 pi) + 1/2) mod L, value exp(2 pi i l / L)
  * (HG_PHASE_QUANTISED, and HG_BINARY_PHASE with L = 2); C is the identity or
@@ -135,7 +147,8 @@ hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illu
  * phase + b H W, levels + b H W and nmse + b (iterations + 1); the
  * illumination (or NULL) is shared.  1 <= batch <= 65535 and
  * batch H W < 2^32.  workspace: hg_workspace_bytes_batched(plan, batch)
- * bytes (the fields of all items are resident together). */
+ * bytes (the fields of all items are resident together).  HG_FOURIER and
+ * HG_FRESNEL plans only (HG_ANGULAR: HG_ERR_INVALID_ARGUMENT). */
 size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch);
 hg_status hg_gs_iterate_batched(hg_plan plan, int32_t batch, const float* target_amp, const float* illumination,
                                 float* phase, uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
@@ -157,9 +170,9 @@ hg_status hg_ospr(hg_plan plan, const float* target_amp, const float* sub_phase,
  * `iterations` iterations runs one GS step per plane j = 0..n_planes-1 on
  * the same SLM state,
  *   R_j = FFT2(Q1_j H);  H = A P(conj(Q1_j) IFFT2(T_j R_j / |R_j|)),
- * with Q1_j the source chirp of plans[j] (1 for a HG_FOURIER plan) and P and
- * the start constraint as in hg_gs_iterate.  All plans share width, height,
- * modulation and levels.  target_amp [n_planes][H][W] centred; phase, levels
+ * with Q1_j the source chirp of plans[j] (1 for a HG_FOURIER plan; no
+ * HG_ANGULAR plans) and P and the start constraint as in hg_gs_iterate.  All
+ * plans share width, height, modulation and levels.  target_amp [n_planes][H][W] centred; phase, levels
  * and illumination as in hg_gs_iterate.  nmse [iterations * n_planes +
  * n_planes] or NULL: the error of every step (plane j of iteration k at
  * k n_planes + j), then of the final state at every plane.
@@ -182,8 +195,8 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
 hg_status hg_ospr_pairs(hg_plan plan, const float* target_amp, const float* sub_phase, int32_t n_pairs,
                         uint8_t* holograms, float* intensity, float* nmse, void* workspace, hipStream_t stream);
 
-/* Single-pixel search on a HG_PHASE_QUANTISED or HG_BINARY_PHASE plan
- * (Sec. 7.3: direct binary search HoloGenAlgDSCuda, simulated annealing
+/* Single-pixel search on a HG_PHASE_QUANTISED or HG_BINARY_PHASE plan,
+ * HG_FOURIER or HG_FRESNEL (Sec. 7.3: direct binary search HoloGenAlgDSCuda, simulated annealing
  * HoloGenAlgSACuda, single-pixel replay updates FFTUpdaterCuda).  The state
  * is the level map `levels` [H][W] uint8 (in: start, out: result; values
  * < L).  E = NMSE(|FFT2(Q1 exp(2 pi i l / L))|^2, ifftshift(target_amp)^2).
@@ -207,7 +220,8 @@ hg_status hg_pixel_search(hg_plan plan, const float* target_amp, uint8_t* levels
  * paper's library, whose further algorithms are left to future work (Sec. 8).
  * The parameter is the continuous SLM phase phi; each of the n_planes replay
  * planes j is given by its own plan (all of one width and height; HG_FOURIER
- * or HG_FRESNEL at its own distance; modulation and levels are ignored):
+ * or HG_FRESNEL at its own distance, not HG_ANGULAR; modulation and levels
+ * are ignored):
  *   V_j = Q1_j exp(i phi),  U_j = FFT2(V_j),  I_j = |U_j|^2
  *   L   = sum_j NMSE(I_j, ifftshift(target_amp_j)^2)   (NMSE as in hg_gs_iterate,
  *         sum I_j = (H W)^2 by Parseval)

@@ -98,6 +98,10 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->col.ospr_b_pair, e->col.lds));
   chk(allow_lds(e->row.grad_row, e->row.lds));
   chk(allow_lds(e->col.grad_col, e->col.lds));
+  chk(allow_lds(e->row.as_row, e->row.lds));
+  chk(allow_lds(e->row.as_row_nmse, e->row.lds));
+  chk(allow_lds(e->col.as_fwd, e->col.lds));
+  chk(allow_lds(e->col.as_inv, e->col.lds));
   return err;
 }
 
@@ -154,6 +158,9 @@ struct hg_plan_s {
   float2* inv_post_y = nullptr;
   float2* inv_post_x = nullptr;
   float2* lvl_tab = nullptr;
+  float2* as_ty = nullptr;   // angular spectrum: exp(i k z) exp(-i pi lambda z fy^2) [H]
+  float2* as_tx = nullptr;   //                   exp(-i pi lambda z fx^2) [W]
+  float as_lam2 = 0.f, as_c3 = 0.f, as_inv_hp = 0.f, as_inv_wp = 0.f;
   float2* unit_y = nullptr;  // exp(-2 pi i k / H), k < H: single-pixel replay updates
   float2* unit_x = nullptr;  // exp(-2 pi i k / W), k < W
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
@@ -245,12 +252,21 @@ hg_status validate_desc(const hg_plan_desc* d) {
     if (!find_length(n))
       return fail(HG_ERR_UNSUPPORTED_SIZE, "no transform of length " + std::to_string(n) + " in this build");
   }
-  if (d->propagation != HG_FOURIER && d->propagation != HG_FRESNEL)
-    return fail(HG_ERR_INVALID_ARGUMENT, "propagation must be HG_FOURIER or HG_FRESNEL");
+  if (d->propagation != HG_FOURIER && d->propagation != HG_FRESNEL && d->propagation != HG_ANGULAR)
+    return fail(HG_ERR_INVALID_ARGUMENT, "propagation must be HG_FOURIER, HG_FRESNEL or HG_ANGULAR");
   if (d->propagation == HG_FRESNEL) {
     for (double v : {d->wavelength, d->pixel_pitch, d->distance})
       if (!std::isfinite(v) || !(v > 0.0))
         return fail(HG_ERR_INVALID_ARGUMENT, "Fresnel wavelength, pixel_pitch and distance must be finite and > 0");
+  }
+  if (d->propagation == HG_ANGULAR) {
+    if (!(std::isfinite(d->wavelength) && d->wavelength > 0.0 && std::isfinite(d->pixel_pitch) &&
+          d->pixel_pitch > 0.0 && std::isfinite(d->distance)))
+      return fail(HG_ERR_INVALID_ARGUMENT,
+                  "angular-spectrum wavelength and pixel_pitch must be finite and > 0, distance finite");
+    if (!(d->wavelength < std::sqrt(2.0) * d->pixel_pitch))
+      return fail(HG_ERR_INVALID_ARGUMENT, "angular spectrum needs pixel_pitch > wavelength / sqrt(2) "
+                                           "(no evanescent components on the grid)");
   }
   switch (d->modulation) {
     case HG_PHASE:
@@ -267,6 +283,19 @@ hg_status validate_desc(const hg_plan_desc* d) {
       return fail(HG_ERR_INVALID_ARGUMENT, "modulation must be HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE");
   }
   return HG_OK;
+}
+
+AsTransfer as_transfer(hg_plan p) {
+  AsTransfer t{};
+  t.ty = p->as_ty;
+  t.tx = p->as_tx;
+  t.lam2 = p->as_lam2;
+  t.c3 = p->as_c3;
+  t.inv_hp = p->as_inv_hp;
+  t.inv_wp = p->as_inv_wp;
+  t.H = p->desc.height;
+  t.W = p->desc.width;
+  return t;
 }
 
 hg_status launch_status(const char* what) {
@@ -326,9 +355,12 @@ void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const flo
                    Scalars* out, hipStream_t s) {
   const size_t n = npix(p);
   const int nb = stats_blocks(n);
+  // sum I of a GS state: N_px sum A^2 after the unnormalised FFT2; the
+  // angular-spectrum replay pass sees H W times the unitary field, N_px^2 sum A^2
+  const double a2_scale = p->desc.propagation == HG_ANGULAR ? (double)n * (double)n : (double)n;
   hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, (const double*)w.stats, nb, n, illum ? 1 : 0,
-                     intensity_sum, out);
+                     intensity_sum, a2_scale, out);
 }
 
 // Workspace of the gradient method for `planes` replay planes:
@@ -358,6 +390,8 @@ hg_status validate_planes(const hg_plan* planes, int n_planes) {
   if (n_planes < 1 || n_planes > kMaxPlanes) return fail(HG_ERR_INVALID_ARGUMENT, "n_planes must be in 1..16");
   for (int j = 0; j < n_planes; ++j) {
     if (!planes[j]) return fail(HG_ERR_INVALID_ARGUMENT, "planes[" + std::to_string(j) + "] is NULL");
+    if (planes[j]->desc.propagation == HG_ANGULAR)
+      return fail(HG_ERR_INVALID_ARGUMENT, "planes must be HG_FOURIER or HG_FRESNEL plans");
     if (planes[j]->desc.width != planes[0]->desc.width || planes[j]->desc.height != planes[0]->desc.height)
       return fail(HG_ERR_INVALID_ARGUMENT, "all planes must have the same width and height");
   }
@@ -393,7 +427,7 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
     hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, (const float*)nullptr, n,
                        stats);
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
-                       (double)n * (double)n, sc + j);
+                       (double)n * (double)n, (double)n, sc + j);
   }
   GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
   fa.field = field;
@@ -459,6 +493,74 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
     }
   }
   return launch_status("gradient launch");
+}
+
+// Gerchberg-Saxton on the angular-spectrum model (one hologram).  Four passes
+// per iteration: column FFT * T inverse column FFT; replay row pass (inverse
+// row FFT -> NMSE, T R / |R| -> row FFT); column FFT * conj T inverse column
+// FFT; SLM row pass (the Fourier-type GS row pass).
+hg_status gs_run_angular(hg_plan p, const float* target_amp, const float* illumination, float* phase,
+                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
+  const int W = p->desc.width, H = p->desc.height;
+  Workspace w = carve(p, workspace, 1);
+  const RowKernels& rk = p->row->row;
+  const ColKernels& ck = p->col->col;
+  GsRowArgs ra{};
+  ra.field = w.field;
+  ra.illum = illumination;
+  ra.H = H;
+  ra.slm.lvl_tab = p->lvl_tab;
+  ra.slm.levels = p->levels;
+  ra.slm.inv_delta = p->levels ? (float)((double)p->levels / (2.0 * M_PI)) : 0.0f;
+  ra.slm.inv_delta_f64 = p->levels ? (double)p->levels / (2.0 * M_PI) : 0.0;
+  ra.slm.half_step = p->levels ? make_float2((float)std::cos(M_PI / p->levels), (float)std::sin(M_PI / p->levels))
+                               : make_float2(1.0f, 0.0f);
+  ra.tw = p->tw_row[0];
+  ra.twr = p->tw_row[1];
+  AsColArgs ca{};
+  ca.io = w.field;
+  ca.W = W;
+  ca.tr = as_transfer(p);
+  ca.scale = 1.0f;
+  ca.tw = p->tw_col[0];
+  ca.twr = p->tw_col[1];
+  AsRowArgs xa{};
+  xa.field = w.field;
+  xa.H = H;
+  xa.target = target_amp;
+  xa.sc = w.sc;
+  xa.tw = p->tw_row[0];
+  xa.twr = p->tw_row[1];
+  const int mode = p->levels == 0 ? GS_CONT
+                 : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
+  void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][0];
+  if (nmse) enqueue_stats(p, w, target_amp, illumination, 0.0, w.sc, stream);
+  const dim3 rows(p->row_blocks), tiles(p->col_blocks);
+  ra.phase0 = phase;
+  ra.phase_out = iterations == 0 ? phase : nullptr;
+  ra.levels_out = iterations == 0 ? levels : nullptr;
+  hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, ra);
+  int chunk0 = 0;
+  for (int k = 0; k <= iterations; ++k) {
+    const bool last = k == iterations;
+    if (last && !nmse) break;
+    hipLaunchKernelGGL(ck.as_fwd, tiles, dim3(ck.threads), ck.lds, stream, ca);
+    xa.partials = nmse ? w.partials + (size_t)(k - chunk0) * p->row_blocks : nullptr;
+    hipLaunchKernelGGL(last ? rk.as_row_nmse : rk.as_row, rows, dim3(rk.threads), rk.lds, stream, xa);
+    if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
+      hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1, 1), dim3(STATS_THREADS), 0, stream,
+                         (const float*)w.partials, p->row_blocks, (const Scalars*)w.sc, nmse + chunk0, (size_t)0,
+                         (size_t)0);
+      chunk0 = k + 1;
+    }
+    if (last) break;
+    hipLaunchKernelGGL(ck.as_inv, tiles, dim3(ck.threads), ck.lds, stream, ca);
+    ra.phase_out = k == iterations - 1 ? phase : nullptr;
+    ra.levels_out = k == iterations - 1 ? levels : nullptr;
+    void (*gs_row)(GsRowArgs) = (illumination || ra.phase_out) ? rk.gs_row_general : gs_row_hot;
+    hipLaunchKernelGGL(gs_row, rows, dim3(rk.threads), rk.lds, stream, ra);
+  }
+  return launch_status("hg_gs_iterate launch");
 }
 
 // Gerchberg-Saxton on `batch` same-shape holograms stacked along the slowest
@@ -623,6 +725,25 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
       st = upload(p, to_f32(re, im), &p->lvl_tab);
     }
   }
+  if (st == HG_OK && desc->propagation == HG_ANGULAR) {
+    const double lam = desc->wavelength, pitch = desc->pixel_pitch, z = desc->distance;
+    const double kz = 2.0 * M_PI * std::fmod(z / lam, 1.0);
+    for (int axis = 0; axis < 2 && st == HG_OK; ++axis) {
+      const int m = axis == 0 ? H : W;
+      std::vector<double> re(m), im(m);
+      for (int k = 0; k < m; ++k) {
+        const double f = (double)(k < (m + 1) / 2 ? k : k - m) / ((double)m * pitch);
+        const double ph = std::fmod(-M_PI * lam * z * f * f, 2.0 * M_PI) + (axis == 0 ? kz : 0.0);
+        re[k] = std::cos(ph);
+        im[k] = std::sin(ph);
+      }
+      st = upload(p, to_f32(re, im), axis == 0 ? &p->as_ty : &p->as_tx);
+    }
+    p->as_lam2 = (float)(lam * lam);
+    p->as_c3 = (float)(M_PI * lam * lam * lam * z);
+    p->as_inv_hp = (float)(1.0 / ((double)H * pitch));
+    p->as_inv_wp = (float)(1.0 / ((double)W * pitch));
+  }
   for (int axis = 0; axis < 2 && st == HG_OK; ++axis) {
     const int m = axis == 0 ? H : W;
     std::vector<double> re(m), im(m);
@@ -686,6 +807,23 @@ hg_status hg_propagate(hg_plan p, const void* in_c64, void* out_c64, int32_t dir
   }
   const RowKernels& rk = p->row->row;
   const ColKernels& ck = p->col->col;
+  if (p->desc.propagation == HG_ANGULAR) {
+    // row FFT -> column FFT * T (conj T back) inverse column FFT, 1/(H W) -> inverse row FFT
+    PropRowArgs r1 = ra;
+    launch(p, HG_KERNEL_PROP_ROW, stream, rk.prop_fwd, p->row_blocks, rk.threads, rk.lds, r1);
+    AsColArgs ac{};
+    ac.io = static_cast<float2*>(out_c64);
+    ac.W = W;
+    ac.tr = as_transfer(p);
+    ac.scale = (float)(1.0 / ((double)W * (double)H));
+    ac.tw = p->tw_col[0];
+    ac.twr = p->tw_col[1];
+    launch(p, HG_KERNEL_PROP_COL, stream, fwd ? ck.as_fwd : ck.as_inv, p->col_blocks, ck.threads, ck.lds, ac);
+    PropRowArgs r2 = ra;
+    r2.in = static_cast<const float2*>(out_c64);
+    launch(p, HG_KERNEL_PROP_ROW, stream, rk.prop_inv, p->row_blocks, rk.threads, rk.lds, r2);
+    return launch_status("hg_propagate launch");
+  }
   launch(p, HG_KERNEL_PROP_ROW, stream, fwd ? rk.prop_fwd : rk.prop_inv, p->row_blocks, rk.threads, rk.lds, ra);
   launch(p, HG_KERNEL_PROP_COL, stream, fwd ? ck.prop_fwd : ck.prop_inv, p->col_blocks, ck.threads, ck.lds, ca);
   return launch_status("hg_propagate launch");
@@ -695,6 +833,8 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
   const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
   if (st != HG_OK) return st;
+  if (p->desc.propagation == HG_ANGULAR)
+    return gs_run_angular(p, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
   return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
 }
 
@@ -709,6 +849,8 @@ hg_status hg_gs_iterate_batched(hg_plan p, int32_t batch, const float* target_am
   const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
   if (st != HG_OK) return st;
   if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
+  if (p->desc.propagation == HG_ANGULAR)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_batched takes HG_FOURIER or HG_FRESNEL plans");
   if ((size_t)batch * npix(p) > (size_t)UINT32_MAX)
     return fail(HG_ERR_INVALID_ARGUMENT, "batch * width * height must be below 2^32");
   return gs_run(p, batch, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
@@ -826,6 +968,8 @@ hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, c
   if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (!p->lvl_tab || p->levels < 2)
     return fail(HG_ERR_INVALID_ARGUMENT, "hg_pixel_search needs a HG_PHASE_QUANTISED or HG_BINARY_PHASE plan");
+  if (p->desc.propagation == HG_ANGULAR)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_pixel_search takes HG_FOURIER or HG_FRESNEL plans");
   if (!target_amp || !levels) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp and levels are required");
   if (n_trials < 0) return fail(HG_ERR_INVALID_ARGUMENT, "n_trials must be >= 0");
   if (n_trials > 0 && !trials) return fail(HG_ERR_INVALID_ARGUMENT, "trials is NULL");
@@ -949,7 +1093,7 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
     if (nmse) {
       hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, illumination, n, stats);
       hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n,
-                         illumination ? 1 : 0, 0.0, sc + j);
+                         illumination ? 1 : 0, 0.0, (double)n, sc + j);
     }
   }
   auto chirp_of = [&](int j, const float2*& qy, const float2*& qx) {

@@ -732,6 +732,135 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
 }
 
 // ===========================================================================
+// Angular-spectrum propagation: T(ky, kx) = exp(2 pi i z sqrt(1/lambda^2 - s)),
+// s = fx^2 + fy^2, on the SLM's own grid (no evanescent components: the plan
+// requires pitch > lambda / sqrt 2).  The phase, up to 2 pi z / lambda, is far
+// beyond FP32; it is split as
+//   k z - pi lambda z fy^2 - pi lambda z fx^2 - delta,
+//   delta = pi lambda^3 z s^2 / (1 + r)^2,  r = sqrt(1 - lambda^2 s),
+// where the first three are FP64-built per-axis tables (exp(i k z) folded
+// into the row table) and delta, at most a few radians, is evaluated in FP32
+// from s without cancellation.
+// ===========================================================================
+struct AsTransfer {
+  const float2* ty;   // exp(i k z) exp(-i pi lambda z fy^2), FFT order [H]
+  const float2* tx;   // exp(-i pi lambda z fx^2), FFT order [W]
+  float lam2;         // lambda^2
+  float c3;           // pi lambda^3 z
+  float inv_hp, inv_wp;  // 1 / (H p), 1 / (W p)
+  int H, W;
+  // transfer at FFT indices (ky, kx); conjugate when CONJ
+  template <bool CONJ>
+  __device__ __forceinline__ float2 at(int ky, int kx) const {
+    const float fy = (float)(ky < (H + 1) / 2 ? ky : ky - H) * inv_hp;
+    const float fx = (float)(kx < (W + 1) / 2 ? kx : kx - W) * inv_wp;
+    const float sq = fmaf(fy, fy, fx * fx);
+    const float r = sqrtf(fmaf(-lam2, sq, 1.0f));
+    const float onep = 1.0f + r;
+    const float delta = c3 * sq * sq / (onep * onep);
+    float sn, cs;
+    sincosf(delta, &sn, &cs);
+    const float2 t = cmul(cmul(ty[ky], tx[kx]), make_float2(cs, -sn));
+    return CONJ ? make_float2(t.x, -t.y) : t;
+  }
+};
+
+struct AsColArgs {
+  float2* io;          // row-transformed field [H][W]; the column pass finishes the transfer
+  int W;
+  AsTransfer tr;
+  float scale;         // applied on store (1 / (H W) for hg_propagate, 1 in the GS loop)
+  const float2* tw;
+  const float2* twr;
+};
+
+// Column FFT -> * T (or conj T, DIR = -1) -> inverse column FFT.
+template <int N, int DIR>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
+  using C = ColCfg<N>;
+  using P = typename C::P;
+  using LL = ColLds<N>;
+  using L0 = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  using LB = Layout<P, true, true>;
+  const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * C::C + c;
+  const bool live = col < a.W;
+  const uint32_t x = live ? col : a.W - 1;
+  LdsView<C::C> lds{hg_dyn_lds + c};
+  float2 v[P::REGS];
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)y * a.W + x); });
+  issue_loads_here();
+  using TW = PassTwiddles<P, C::THREADS, true, true>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+  for_layout<L1>(t, [&](int s, int ky) { v[s] = cmul(v[s], a.tr.template at<(DIR < 0)>(ky, (int)x)); });
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+  if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.io, (uint32_t)y * a.W + x, cscale(v[s], a.scale)); });
+}
+
+struct AsRowArgs {
+  float2* field;
+  int H;
+  const float* target;   // target amplitude [H][W], centred = natural order on this grid
+  const Scalars* sc;
+  float* partials;       // one float per workgroup; null -> no NMSE
+  const float2* tw;
+  const float2* twr;
+};
+
+// Replay pass of GS on the angular-spectrum model: inverse row FFT (R on the
+// SLM grid) -> NMSE partial -> REPLACE: T R / |R| -> row FFT -> field.
+template <int N, bool REPLACE>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
+  using C = RowCfg<N>;
+  using P = typename C::P;
+  using LL = RowLds<N>;
+  using LI = Layout<P, true, false>;
+  using LF = Layout<P, false, false>;
+  using L1 = Layout<P, false, true>;
+  __shared__ float red[C::THREADS / 64];
+  const RowTeam<C> rt(a.H);
+  const int t = rt.t;
+  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  float2 v[P::REGS];
+  const uint32_t row = (uint32_t)rt.y * N;
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  float tg[P::REGS];
+  for_layout<LF>(t, [&](int s, int x) { tg[s] = ldg(a.target, row + x); });
+  issue_loads_here();
+  using TW = PassTwiddles<P, C::THREADS, true, true>;
+  TW tw;
+  tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+  const bool nm = a.partials != nullptr;
+  const float sa = nm ? a.sc->a : 0.f, sb = nm ? a.sc->b : 0.f;
+  float acc = 0.f;
+  for_layout<LF>(t, [&](int s, int) {
+    const float2 R = v[s];
+    const float tv = tg[s];
+    const float I = cnorm(R);
+    const float d = fmaf(I, sa, -(tv * tv * sb));
+    acc = fmaf(d, d, acc);
+    if constexpr (REPLACE) {
+      const float k = tv * rsqrtf(I);
+      v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(tv, 0.0f);
+    }
+  });
+  if (nm) {
+    const float sum = block_sum<C::THREADS>(rt.live ? acc : 0.0f, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = sum;
+  }
+  if constexpr (REPLACE) {
+    tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+  }
+}
+
+// ===========================================================================
 // OSPR
 // ===========================================================================
 struct OsprRowArgs {
@@ -893,6 +1022,8 @@ struct RowKernels {
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
   void (*grad_row)(GradRowArgs);
+  void (*as_row)(AsRowArgs);
+  void (*as_row_nmse)(AsRowArgs);
   int teams, threads;
   size_t lds;
 };
@@ -904,6 +1035,8 @@ struct ColKernels {
   void (*grad_col)(GsColArgs);
   void (*ospr_b)(OsprColArgs);
   void (*ospr_b_pair)(OsprColArgs);
+  void (*as_fwd)(AsColArgs);
+  void (*as_inv)(AsColArgs);
   int cols, threads;
   size_t lds;
 };
@@ -945,11 +1078,13 @@ LengthEntry make_length_entry() {
   e.row.ospr_a = k_ospr_a<N>;
   e.row.ospr_c = k_ospr_c<N>;
   e.row.grad_row = k_grad_row<N>;
+  e.row.as_row = k_as_row<N, true>;
+  e.row.as_row_nmse = k_as_row<N, false>;
   e.row.teams = RowCfg<N>::TEAMS;
   e.row.threads = RowCfg<N>::THREADS;
   e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
-           k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>,
+           k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
   using PR = typename RowCfg<N>::P;
   using PC = typename ColCfg<N>::P;

@@ -78,10 +78,12 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_partial(const float* __
   }
 }
 
-// Combine the partials; sum I follows from Parseval: N_px sum A^2 for a GS
-// state (|H| = A), N_px^2 for an OSPR average of +-1 holograms (intensity_sum).
+// Combine the partials; sum I follows from Parseval: a2_scale sum A^2 for a
+// GS state (|H| = A; a2_scale = N_px through one unnormalised FFT2, N_px^2
+// through the unnormalised angular-spectrum round trip), or the given
+// intensity_sum (N_px^2 for an OSPR average of +-1 holograms).
 __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __restrict__ part, int nblk, size_t n,
-                                                               int has_illum, double intensity_sum,
+                                                               int has_illum, double intensity_sum, double a2_scale,
                                                                Scalars* __restrict__ sc) {
   __shared__ double red[STATS_THREADS];
   double t2 = 0.0, t4 = 0.0, a2 = 0.0;
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __r
   if (threadIdx.x == 0) {
     const double npx = (double)n;
     if (!has_illum) a2 = npx;
-    const double s_i = intensity_sum > 0.0 ? intensity_sum : npx * a2;
+    const double s_i = intensity_sum > 0.0 ? intensity_sum : a2_scale * a2;
     sc->sum_t2 = t2;
     sc->sum_t4 = t4;
     sc->sum_a2 = a2;

@@ -22,6 +22,7 @@ HG_ERR_INTERNAL = 5
 
 HG_FOURIER = 0
 HG_FRESNEL = 1
+HG_ANGULAR = 2
 HG_PHASE = 0
 HG_PHASE_QUANTISED = 1
 HG_BINARY_PHASE = 2
