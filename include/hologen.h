@@ -146,7 +146,7 @@ hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illu
  * call per shape on one stream.  Item b uses target_amp + b H W,
  * phase + b H W, levels + b H W and nmse + b (iterations + 1); the
  * illumination (or NULL) is shared.  1 <= batch <= 65535 and
- * batch H W < 2^32.  workspace: hg_workspace_bytes_batched(plan, batch)
+ * batch H W4 < 2^32 (W4 = W rounded up to a multiple of 4).  workspace: hg_workspace_bytes_batched(plan, batch)
  * bytes (the fields of all items are resident together).  HG_FOURIER and
  * HG_FRESNEL plans only (HG_ANGULAR: HG_ERR_INVALID_ARGUMENT). */
 size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch);

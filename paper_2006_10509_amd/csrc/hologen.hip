@@ -165,6 +165,7 @@ struct hg_plan_s {
   float2* unit_x = nullptr;  // exp(-2 pi i k / W), k < W
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
   int row_blocks = 0, col_blocks = 0;
+  int ft = 0;              // GS-family field layout: 0 row order, else column tile width
   size_t ws_bytes = 0;     // workspace of one hologram (ws_layout(p, 1).total)
   std::vector<void*> allocations;
   // diagnostics: event pairs around launches of one kernel kind
@@ -304,7 +305,8 @@ hg_status launch_status(const char* what) {
   return HG_OK;
 }
 
-// Workspace of `batch` same-shape holograms: fields [batch][H][W] complex64 |
+// Workspace of `batch` same-shape holograms: fields [batch] complex64 in the
+// GS layout |
 // Scalars [batch] | stats | NMSE partials [batch][kNmseChunk][workgroups] |
 // tiled targets [batch][tiles][H][C].  batch = 1 is the single-call layout.
 struct WsLayout {
@@ -312,8 +314,13 @@ struct WsLayout {
   size_t partial_stride, target_stride;   // floats per batch item
 };
 
+// Complex elements of one field in the plan's GS-family layout.
+size_t field_elems(hg_plan p) {
+  return (size_t)field_width((uint32_t)p->desc.width, (uint32_t)p->ft) * (size_t)p->desc.height;
+}
+
 WsLayout ws_layout(hg_plan p, int batch) {
-  const size_t n = (size_t)p->desc.width * (size_t)p->desc.height;
+  const size_t n = field_elems(p);
   const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
   WsLayout L{};
   L.partial_stride = (size_t)kNmseChunk * nwg;
@@ -373,7 +380,7 @@ struct GradLayout {
 GradLayout grad_layout(hg_plan p, int planes) {
   const size_t n = npix(p);
   GradLayout g{};
-  g.acc = align_up(n * sizeof(float2));
+  g.acc = align_up(field_elems(p) * sizeof(float2));
   g.sc = g.acc + align_up(n * sizeof(float));
   g.stats = g.sc + align_up((size_t)planes * sizeof(Scalars));
   g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
@@ -430,18 +437,21 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
                        (double)n * (double)n, (double)n, sc + j);
   }
   GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
+  fa.ft = p0->ft;
   fa.field = field;
   fa.phase0 = phase;
   fa.H = H;
   fa.tw = p0->tw_row[0];
   fa.twr = p0->tw_row[1];
   GsColArgs ca{};
+  ca.ft = p0->ft;
   ca.field = field;
   ca.W = W;
   ca.H = H;
   ca.tw = p0->tw_col[0];
   ca.twr = p0->tw_col[1];
   GradRowArgs ga{};
+  ga.ft = p0->ft;
   ga.field = field;
   ga.phase = phase;
   ga.H = H;
@@ -506,6 +516,7 @@ hg_status gs_run_angular(hg_plan p, const float* target_amp, const float* illumi
   const RowKernels& rk = p->row->row;
   const ColKernels& ck = p->col->col;
   GsRowArgs ra{};
+  ra.ft = p->ft;
   ra.field = w.field;
   ra.illum = illumination;
   ra.H = H;
@@ -518,6 +529,7 @@ hg_status gs_run_angular(hg_plan p, const float* target_amp, const float* illumi
   ra.tw = p->tw_row[0];
   ra.twr = p->tw_row[1];
   AsColArgs ca{};
+  ca.ft = p->ft;
   ca.io = w.field;
   ca.W = W;
   ca.tr = as_transfer(p);
@@ -525,6 +537,7 @@ hg_status gs_run_angular(hg_plan p, const float* target_amp, const float* illumi
   ca.tw = p->tw_col[0];
   ca.twr = p->tw_col[1];
   AsRowArgs xa{};
+  xa.ft = p->ft;
   xa.field = w.field;
   xa.H = H;
   xa.target = target_amp;
@@ -576,10 +589,12 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   const ColKernels& ck = p->col->col;
 
   GsRowArgs ra{};
+  ra.ft = p->ft;
   ra.field = w.field;
   ra.illum = illumination;
   ra.H = H;
   ra.px = (uint32_t)n;
+  ra.fpx = (uint32_t)field_elems(p);
   if (p->desc.propagation == HG_FRESNEL) {
     ra.q1y = p->q1y;
     ra.q1x = p->q1x;
@@ -600,6 +615,7 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
                        w.target + (size_t)b * L.target_stride, H, W, cols, tiled_n);
 
   GsColArgs ca{};
+  ca.ft = p->ft;
   ca.field = w.field;
   ca.W = W;
   ca.H = H;
@@ -607,7 +623,7 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   ca.sc = w.sc;
   ca.tw = p->tw_col[0];
   ca.twr = p->tw_col[1];
-  ca.px = (uint32_t)n;
+  ca.px = (uint32_t)field_elems(p);
   ca.target_stride = (uint32_t)L.target_stride;
   ca.partial_stride = (uint32_t)L.partial_stride;
 
@@ -759,6 +775,9 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   }
   p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
   p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
+  // Tiles of the column pass's width where the row kernels are compiled for
+  // that width (whole-line accesses on both passes); row order elsewhere.
+  p->ft = p->row->row.ft != 0 && p->row->row.ft == p->col->col.cols ? p->col->col.cols : 0;
   const size_t n = (size_t)W * H;
   p->ws_bytes = ws_layout(p, 1).total;
   *out = p;
@@ -851,8 +870,8 @@ hg_status hg_gs_iterate_batched(hg_plan p, int32_t batch, const float* target_am
   if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
   if (p->desc.propagation == HG_ANGULAR)
     return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_batched takes HG_FOURIER or HG_FRESNEL plans");
-  if ((size_t)batch * npix(p) > (size_t)UINT32_MAX)
-    return fail(HG_ERR_INVALID_ARGUMENT, "batch * width * height must be below 2^32");
+  if ((size_t)batch * field_elems(p) > (size_t)UINT32_MAX)
+    return fail(HG_ERR_INVALID_ARGUMENT, "batch * height * (width rounded up to a multiple of 4) must be below 2^32");
   return gs_run(p, batch, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
 }
 
@@ -1102,6 +1121,7 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
     qx = fres ? planes[j]->q1x : nullptr;
   };
   GsRowArgs ra{};
+  ra.ft = p0->ft;
   ra.field = field;
   ra.illum = illumination;
   ra.H = H;
@@ -1114,6 +1134,7 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
   ra.tw = p0->tw_row[0];
   ra.twr = p0->tw_row[1];
   GsColArgs ca{};
+  ca.ft = p0->ft;
   ca.field = field;
   ca.W = W;
   ca.H = H;

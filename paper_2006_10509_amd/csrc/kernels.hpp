@@ -196,19 +196,84 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
 }
 
+// ---------------------------------------------------------------------------
+// Field layout of the Gerchberg-Saxton family (GS, multi-plane GS, gradient,
+// angular-spectrum GS) between its row and column passes, chosen per plan:
+//   ft = 0: row order, element (y, x) at y W + x;
+//   ft > 0: column tiles of ft (the column pass's tile width), stored one
+//           tile after another, each row by row: (y, x) at
+//           ((x / ft) H + y) ft + x % ft, the width rounded up to a multiple
+//           of ft (the padding is never read).
+// Tiled, a column pass moves contiguous blocks instead of ft * 8-byte row
+// segments, and a row pass whose workgroup interleaves its rows across the
+// lanes (RowTeam) still moves whole lines.  A row kernel of length N is
+// compiled for one tile width, RowTeam<RowCfg<N>>::FT (0: row order only);
+// a plan is tiled when that width equals its column pass's.  Propagation,
+// OSPR and the single-pixel search keep row order.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr uint32_t field_width(uint32_t w, uint32_t ft) { return ft ? (w + ft - 1) / ft * ft : w; }
+
+// Row and thread of a row-pass thread; rows are packed TEAMS to a workgroup.
+// With a tiled field and teams that synchronise through s_barrier, groups of
+// ft consecutive lanes take consecutive rows, so one access of a wavefront
+// covers ft-wide tile pieces of several rows; otherwise team = thread / T.
 template <class C>
 struct RowTeam {
+  using P = typename C::P;
+  // Tile width of the tiled layout these row kernels take (0: none).  The
+  // teams must interleave (s_barrier exchanges, several rows) and every
+  // register slot must lie a multiple of FT from t.
+  static constexpr int FT = C::FT;
+  static_assert(FT == 0 || (!C::WAVE_SYNC && C::TEAMS > 1 && (FT & (FT - 1)) == 0 && P::T % FT == 0 &&
+                            Layout<P, true, false>::STRIDE % FT == 0 && Layout<P, false, true>::STRIDE % FT == 0),
+                "tile width unusable with this row shape");
   int t, team, y;
   bool live;
-  __device__ __forceinline__ RowTeam(int H) {
-    using P = typename C::P;
-    team = threadIdx.x / P::T;
-    t = threadIdx.x % P::T;
+  // ft: the field's tile width, 0 or FT
+  __device__ __forceinline__ RowTeam(int H, int ft = 0) {
+    if (FT && ft) {
+      team = (threadIdx.x / FT) % C::TEAMS;
+      t = threadIdx.x % FT + FT * (threadIdx.x / (FT * C::TEAMS));
+    } else {
+      team = threadIdx.x / P::T;
+      t = threadIdx.x % P::T;
+    }
     int row = blockIdx.x * C::TEAMS + team;
-    if constexpr (P::T == 64) row = __builtin_amdgcn_readfirstlane(row);
+    if constexpr (!FT && P::T == 64) row = __builtin_amdgcn_readfirstlane(row);
     live = row < H;
     y = live ? row : H - 1;
   }
+};
+
+// Offsets of one thread's elements of row y in the field: the element at x
+// (a register slot's position, a compile-time distance x - t from t, a
+// multiple of FT) lies at base + (x - t) step.
+struct RowField {
+  uint32_t base, step;
+  int t;
+  template <int N, int FT>
+  __device__ __forceinline__ static RowField make(int t, int y, int H, int ft) {
+    if (FT && ft) return {(((uint32_t)t / FT) * (uint32_t)H + (uint32_t)y) * FT + (uint32_t)t % FT, (uint32_t)H, t};
+    return {(uint32_t)y * N + (uint32_t)t, 1u, t};
+  }
+  __device__ __forceinline__ uint32_t at(int x) const { return base + (uint32_t)(x - t) * step; }
+};
+
+// Offsets of one column of a column pass of tile width CT: element y at
+// base + y step (ft: the field's tile width, 0 or CT).
+template <int CT>
+struct ColField {
+  uint32_t base, step;
+  __device__ __forceinline__ ColField(uint32_t x, int W, int H, int ft) {
+    if (ft) {
+      base = (x / CT) * (uint32_t)H * CT + x % CT;
+      step = CT;
+    } else {
+      base = x;
+      step = (uint32_t)W;
+    }
+  }
+  __device__ __forceinline__ uint32_t at(int y) const { return base + (uint32_t)y * step; }
 };
 
 // Wavefront then workgroup sum of one float per thread, fixed order.
@@ -244,7 +309,10 @@ template <int N>
 struct RowLds {
   using C = RowCfg<N>;
   using P = typename C::P;
-  static constexpr int TWF = C::TEAMS * lds_len(N);
+  // a team's exchange region, padded to 4 mod 16 complex values so that the
+  // interleaved teams of one wavefront start on different LDS banks
+  static constexpr int TEAM = lds_len(N) + (20 - lds_len(N) % 16) % 16;
+  static constexpr int TWF = C::TEAMS * TEAM;
   static constexpr int TAB = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
   static constexpr int WORDS = TAB + N;
 };
@@ -301,7 +369,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) 
   using L1 = Layout<P, false, true>;
   const RowTeam<C> rt(a.H);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.in, row + wrap_add<N>(x, a.sx_in)); });
@@ -380,12 +448,14 @@ struct GsRowArgs {
   int q_out_set;
   const float2* qoy;
   const float2* qox;
-  uint32_t px;              // batch: pixels per hologram; item blockIdx.y is offset by blockIdx.y * px
+  uint32_t px;              // batch: pixels per hologram (row-order arrays)
+  uint32_t fpx;             // batch: field elements per hologram
+  int ft;                   // field layout (RowTeam, RowField)
   // Batch item blockIdx.y of a launch over a stack of same-shape holograms
   // (gridDim.y items; the illumination is shared).
   __device__ __forceinline__ void select_item() {
     const uint32_t off = blockIdx.y * px;
-    field += off;
+    field += blockIdx.y * fpx;
     if (phase0) phase0 += off;
     if (phase_out) phase_out += off;
     if (levels_out) levels_out += off;
@@ -417,9 +487,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
   using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   float ph[P::REGS];
@@ -451,7 +521,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
     v[s] = h;
   });
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, row + x, v[s]); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, f.at(x), v[s]); });
 }
 
 // exp(i o pi / 4) for an octant index o in [0, 8), from the index bits: the
@@ -509,13 +580,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   using L1 = Layout<P, false, true>;
   static_assert(LF::R == Layout<P, true, true>::R, "layout mismatch");
   constexpr bool GENERAL = MODE < 0;
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   const bool fres = GENERAL ? (a.q1y != nullptr) : FRES;
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, row + x); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;
   using QX = RowTable<N, LF>;
@@ -559,7 +631,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
     });
   }
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, row + x, v[s]); });
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, f.at(x), v[s]); });
 }
 
 struct GsColArgs {
@@ -571,9 +643,10 @@ struct GsColArgs {
   float* partials;            // one float per workgroup for this state; null -> no NMSE
   const float2* tw;
   const float2* twr;
-  // batch strides of item blockIdx.y: field pixels, tiled-target floats,
-  // partial floats (the Scalars advance by one per item)
+  // batch strides of item blockIdx.y: field elements (tiled layout),
+  // tiled-target floats, partial floats (the Scalars advance by one per item)
   uint32_t px, target_stride, partial_stride;
+  int ft;                     // field layout (ColField)
   __device__ __forceinline__ void select_item() {
     const uint32_t b = blockIdx.y;
     field += b * px;
@@ -610,7 +683,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.field, (uint32_t)y * a.W + x); });
+  const ColField<C::C> f(x, a.W, N, a.ft);
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.field, f.at(y)); });
   float tgt[P::REGS];
   const uint32_t tbase = (uint32_t)tile * N * C::C + c;
   for_layout<L1>(t, [&](int s, int ky) { tgt[s] = ldg(a.target, tbase + (uint32_t)ky * C::C); });
@@ -646,7 +720,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   }
   if constexpr (BACK) {
     tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
-    if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, (uint32_t)y * a.W + x, v[s]); });
+    if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, f.at(y), v[s]); });
   }
 }
 
@@ -655,6 +729,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
 // ===========================================================================
 struct GradRowArgs {
   const float2* field;     // output of the COL_GRAD pass of this plane
+  int ft;                  // its layout (RowField)
   float* phase;            // SLM phase phi [H][W]; updated in place by the Adam step
   int H;
   const float2* q1y;       // source chirp of this plane; null -> Fourier plane
@@ -682,12 +757,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
   using LL = RowLds<N>;
   using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
   using LF = Layout<P, false, false>;  // its last stage
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
   float ph[P::REGS], ac[P::REGS], mm[P::REGS], vv[P::REGS];
   const bool adam = a.last && a.m != nullptr;
   for_layout<LF>(t, [&](int s, int x) {
@@ -766,8 +842,9 @@ struct AsTransfer {
 };
 
 struct AsColArgs {
-  float2* io;          // row-transformed field [H][W]; the column pass finishes the transfer
+  float2* io;          // row-transformed field; the column pass finishes the transfer
   int W;
+  int ft;              // field layout (ColField): 0 for propagation
   AsTransfer tr;
   float scale;         // applied on store (1 / (H W) for hg_propagate, 1 in the GS loop)
   const float2* tw;
@@ -789,7 +866,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, (uint32_t)y * a.W + x); });
+  const ColField<C::C> f(x, a.W, N, a.ft);
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, f.at(y)); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;
   TW tw;
@@ -798,12 +876,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   for_layout<L1>(t, [&](int s, int ky) { v[s] = cmul(v[s], a.tr.template at<(DIR < 0)>(ky, (int)x)); });
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
-  if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.io, (uint32_t)y * a.W + x, cscale(v[s], a.scale)); });
+  if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.io, f.at(y), cscale(v[s], a.scale)); });
 }
 
 struct AsRowArgs {
   float2* field;
   int H;
+  int ft;                // field layout (RowField)
   const float* target;   // target amplitude [H][W], centred = natural order on this grid
   const Scalars* sc;
   float* partials;       // one float per workgroup; null -> no NMSE
@@ -822,12 +901,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
   using LF = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   __shared__ float red[C::THREADS / 64];
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
   float tg[P::REGS];
   for_layout<LF>(t, [&](int s, int x) { tg[s] = ldg(a.target, row + x); });
   issue_loads_here();
@@ -856,7 +936,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
   }
   if constexpr (REPLACE) {
     tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, f.at(x), v[s]); });
   }
 }
 
@@ -887,7 +967,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
   using L1 = Layout<P, false, true>;
   const RowTeam<C> rt(a.H);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t srow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   float th[P::REGS], am[P::REGS];
@@ -974,7 +1054,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   __shared__ float red[C::THREADS / 64];
   const RowTeam<C> rt(a.H);
   const int t = rt.t;
-  LdsView<1> lds{hg_dyn_lds + rt.team * lds_len(N)};
+  LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
@@ -1026,6 +1106,7 @@ struct RowKernels {
   void (*as_row_nmse)(AsRowArgs);
   int teams, threads;
   size_t lds;
+  int ft;          // RowTeam<RowCfg<N>>::FT
 };
 struct ColKernels {
   void (*prop_fwd)(PropColArgs);
@@ -1083,6 +1164,7 @@ LengthEntry make_length_entry() {
   e.row.teams = RowCfg<N>::TEAMS;
   e.row.threads = RowCfg<N>::THREADS;
   e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
+  e.row.ft = RowTeam<RowCfg<N>>::FT;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
            k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};

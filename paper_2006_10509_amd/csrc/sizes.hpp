@@ -1,7 +1,10 @@
 // Transform lengths compiled into the library and the launch shape of each.
 //
 // A row pass gives every row (length W, the contiguous axis) to a team of T
-// threads and packs TEAMS rows into one workgroup.  A column pass gives every
+// threads and packs TEAMS rows into one workgroup.  FT is the column tile
+// width of the tiled field layout the GS-family row kernels of that length
+// take (0: row order only; a plan is tiled when its column pass has the same
+// tile width).  A column pass gives every
 // column (length H) to a team and packs C adjacent columns into one
 // workgroup, so each global access covers C * 8 contiguous bytes per row.
 // Teams of at most 64 threads that do not straddle a wavefront exchange data
@@ -15,10 +18,11 @@ namespace hg {
 template <int N> struct RowCfg;
 template <int N> struct ColCfg;
 
-#define HG_ROW_CFG(N_, TEAMS_, T_, ...)                                   \
+#define HG_ROW_CFG(N_, TEAMS_, T_, FT_, ...)                              \
   template <> struct RowCfg<N_> {                                        \
     using P = Plan<N_, T_, __VA_ARGS__>;                                 \
     static constexpr int TEAMS = TEAMS_;                                 \
+    static constexpr int FT = FT_;                                       \
     static constexpr int THREADS = TEAMS_ * T_;                          \
     static constexpr bool WAVE_SYNC = (T_ <= 64) && (64 % T_ == 0);      \
   };
@@ -33,24 +37,27 @@ template <int N> struct ColCfg;
 // The shapes of lengths 512, 1024, 1080, 1920 and 2048 were chosen by timing
 // the GS loop on MI355X over candidate team sizes, radix orders and column
 // tile widths (single holograms and same-shape batches); the rest are
-// untuned defaults.  Wider column tiles (C = 8: 64-byte row segments) win
+// untuned defaults.  The tiled GS layout (FT) measured 5 % faster per 1024^2
+// iteration and level at 2048^2; at 1920 x 1080 (column tiles of 8, row
+// kernels of 1920 compiled for 4) and for rows of 64-thread teams, which
+// cannot interleave, row order is kept.  Wider column tiles (C = 8: 64-byte row segments) win
 // where the frame still gives every CU a tile.
-//          N     rows/WG  T    radices
-HG_ROW_CFG(16,    64,     4,   4, 4)
-HG_ROW_CFG(32,    32,     8,   4, 2, 4)
-HG_ROW_CFG(64,    32,     8,   8, 8)
-HG_ROW_CFG(128,   16,    16,   8, 2, 8)
-HG_ROW_CFG(256,   16,    16,   16, 16)
-HG_ROW_CFG(512,   2,    64,   8, 8, 8)
-HG_ROW_CFG(1024,   2,   128,   8, 4, 4, 8)
-HG_ROW_CFG(2048,   2,   128,   16, 8, 16)
-HG_ROW_CFG(4096,   2,   128,   16, 16, 16)
-HG_ROW_CFG(24,    32,     8,   8, 3)
-HG_ROW_CFG(60,    16,    16,   4, 3, 5)
-HG_ROW_CFG(90,    16,    16,   2, 3, 3, 5)
-HG_ROW_CFG(120,   16,    16,   8, 3, 5)
-HG_ROW_CFG(1080,   4,    64,   8, 3, 3, 3, 5)
-HG_ROW_CFG(1920,   2,   128,   16, 8, 3, 5)
+//          N     rows/WG  T    FT  radices
+HG_ROW_CFG(16,    64,     4,  0,   4, 4)
+HG_ROW_CFG(32,    32,     8,  0,   4, 2, 4)
+HG_ROW_CFG(64,    32,     8,  0,   8, 8)
+HG_ROW_CFG(128,   16,    16,  0,   8, 2, 8)
+HG_ROW_CFG(256,   16,    16,  0,   16, 16)
+HG_ROW_CFG(512,   2,    64,  0,   8, 8, 8)
+HG_ROW_CFG(1024,   2,   128,  4,   8, 4, 4, 8)
+HG_ROW_CFG(2048,   2,   128,  8,   16, 8, 16)
+HG_ROW_CFG(4096,   2,   128,  0,   16, 16, 16)
+HG_ROW_CFG(24,    32,     8,  0,   8, 3)
+HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)
+HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
+HG_ROW_CFG(120,   16,    16,  0,   8, 3, 5)
+HG_ROW_CFG(1080,   4,    64,  0,   8, 3, 3, 3, 5)
+HG_ROW_CFG(1920,   2,   128,  0,   16, 8, 3, 5)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
