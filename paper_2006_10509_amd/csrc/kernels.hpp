@@ -140,13 +140,13 @@ __device__ __forceinline__ void stg(T* base, uint32_t i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
-// Field accesses of the GS passes of length N.  For N <= 1024 they carry the
-// nontemporal hint (each pass reads and writes the field once; measured on the
-// 1024^2 loop it saves about 2 % per iteration).  Longer passes use plain
-// accesses: at 2048^2 the hint made a column pass, whose 32-byte row segments
-// neighbouring workgroups share through L2, 1.5x slower, and on a row pass's
-// stores it slowed the following column pass by about 10 %.  The propagation
-// and OSPR passes use plain accesses throughout.
+// Field accesses of the GS-family passes of length N.  For N <= 1024 they
+// carry the nontemporal hint: each pass reads and writes the field once, and
+// on the tiled 1024^2 loop dropping the hint from any one of its four field
+// accesses costs 11-19 % per iteration.  Longer passes use plain accesses: at
+// 2048^2 the hint costs about 1 % (tiled), and in row order it made a column
+// pass, whose 32-byte row segments neighbouring workgroups share through L2,
+// 1.5x slower.  The propagation and OSPR passes use plain accesses.
 template <int N>
 __device__ __forceinline__ float2 ldg_field(const float2* base, uint32_t i) {
   if constexpr (N <= 1024) {
@@ -166,6 +166,24 @@ __device__ __forceinline__ void stg_field(float2* base, uint32_t i, float2 v) {
   } else {
     stg(base, i, v);
   }
+}
+
+// The same for per-pixel float arrays that a pass streams once (the gradient
+// row pass's phase, accumulator and Adam moments): the hint took 13 % off an
+// Adam step of the three-plane 1024^2 problem.
+template <int N>
+__device__ __forceinline__ float ldg_f(const float* base, uint32_t i) {
+  if constexpr (N <= 1024)
+    return __builtin_nontemporal_load(reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + i * 4u));
+  else
+    return ldg(base, i);
+}
+template <int N>
+__device__ __forceinline__ void stg_f(float* base, uint32_t i, float v) {
+  if constexpr (N <= 1024)
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + i * 4u));
+  else
+    stg(base, i, v);
 }
 
 // Keeps the loads issued above it above it: the scheduler would otherwise sink
@@ -763,14 +781,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
   float ph[P::REGS], ac[P::REGS], mm[P::REGS], vv[P::REGS];
   const bool adam = a.last && a.m != nullptr;
   for_layout<LF>(t, [&](int s, int x) {
-    ph[s] = ldg(a.phase, row + x);
-    ac[s] = a.first ? 0.0f : ldg(a.acc, row + x);
-    mm[s] = adam ? ldg(a.m, row + x) : 0.0f;
-    vv[s] = adam ? ldg(a.v, row + x) : 0.0f;
+    ph[s] = ldg_f<N>(a.phase, row + x);
+    ac[s] = a.first ? 0.0f : ldg_f<N>(a.acc, row + x);
+    mm[s] = adam ? ldg_f<N>(a.m, row + x) : 0.0f;
+    vv[s] = adam ? ldg_f<N>(a.v, row + x) : 0.0f;
   });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, false, true>;
@@ -793,16 +811,16 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
     const float2 G = v[s];
     const float g = fmaf(2.0f, fmaf(V.x, G.y, -(V.y * G.x)), ac[s]);
     if (!a.last) {
-      stg(a.acc, i, g);
+      stg_f<N>(a.acc, i, g);
       return;
     }
-    if (a.grad_out) stg(a.grad_out, i, g);
+    if (a.grad_out) stg_f<N>(a.grad_out, i, g);
     if (adam) {
       const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g);
       const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g * g);
-      stg(a.m, i, m1);
-      stg(a.v, i, v1);
-      stg(a.phase, i, ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps));
+      stg_f<N>(a.m, i, m1);
+      stg_f<N>(a.v, i, v1);
+      stg_f<N>(a.phase, i, ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps));
     }
   });
 }
@@ -867,7 +885,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
   const ColField<C::C> f(x, a.W, N, a.ft);
-  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg(a.io, f.at(y)); });
+  for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.io, f.at(y)); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;
   TW tw;
@@ -876,7 +894,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   for_layout<L1>(t, [&](int s, int ky) { v[s] = cmul(v[s], a.tr.template at<(DIR < 0)>(ky, (int)x)); });
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
-  if (live) for_layout<LB>(t, [&](int s, int y) { stg(a.io, f.at(y), cscale(v[s], a.scale)); });
+  if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.io, f.at(y), cscale(v[s], a.scale)); });
 }
 
 struct AsRowArgs {
@@ -907,7 +925,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
+  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
   float tg[P::REGS];
   for_layout<LF>(t, [&](int s, int x) { tg[s] = ldg(a.target, row + x); });
   issue_loads_here();
@@ -936,7 +954,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
   }
   if constexpr (REPLACE) {
     tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, f.at(x), v[s]); });
+    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, f.at(x), v[s]); });
   }
 }
 
