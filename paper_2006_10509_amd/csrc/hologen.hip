@@ -775,9 +775,10 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   }
   p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
   p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
-  // Tiles of the column pass's width where the row kernels are compiled for
-  // that width (whole-line accesses on both passes); row order elsewhere.
-  p->ft = p->row->row.ft != 0 && p->row->row.ft == p->col->col.cols ? p->col->col.cols : 0;
+  // Tiled where the row kernels are compiled for a tile width that the column
+  // pass's tile width divides (whole-line accesses on both passes); row
+  // order elsewhere.
+  p->ft = p->row->row.ft != 0 && p->row->row.ft % p->col->col.cols == 0 ? p->row->row.ft : 0;
   const size_t n = (size_t)W * H;
   p->ws_bytes = ws_layout(p, 1).total;
   *out = p;

@@ -218,16 +218,17 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // Field layout of the Gerchberg-Saxton family (GS, multi-plane GS, gradient,
 // angular-spectrum GS) between its row and column passes, chosen per plan:
 //   ft = 0: row order, element (y, x) at y W + x;
-//   ft > 0: column tiles of ft (the column pass's tile width), stored one
-//           tile after another, each row by row: (y, x) at
-//           ((x / ft) H + y) ft + x % ft, the width rounded up to a multiple
-//           of ft (the padding is never read).
-// Tiled, a column pass moves contiguous blocks instead of ft * 8-byte row
-// segments, and a row pass whose workgroup interleaves its rows across the
-// lanes (RowTeam) still moves whole lines.  A row kernel of length N is
-// compiled for one tile width, RowTeam<RowCfg<N>>::FT (0: row order only);
-// a plan is tiled when that width equals its column pass's.  Propagation,
-// OSPR and the single-pixel search keep row order.
+//   ft > 0: column tiles of ft (a power of two and a multiple of the column
+//           pass's tile width), stored one tile after another, each row by
+//           row: (y, x) at ((x / ft) H + y) ft + x % ft, the width rounded up
+//           to a multiple of ft (the padding is never read).
+// Tiled, a column pass moves short contiguous runs of whole tiles instead of
+// C * 8-byte row segments spread over the frame, and a row pass whose
+// workgroup interleaves its rows across the lanes (RowTeam) moves whole
+// lines.  A row kernel of length N is compiled for one tile width,
+// RowTeam<RowCfg<N>>::FT (0: row order only); a plan is tiled when that
+// width is a multiple of its column pass's.  Propagation, OSPR and the
+// single-pixel search keep row order.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr uint32_t field_width(uint32_t w, uint32_t ft) { return ft ? (w + ft - 1) / ft * ft : w; }
 
@@ -277,15 +278,15 @@ struct RowField {
   __device__ __forceinline__ uint32_t at(int x) const { return base + (uint32_t)(x - t) * step; }
 };
 
-// Offsets of one column of a column pass of tile width CT: element y at
-// base + y step (ft: the field's tile width, 0 or CT).
-template <int CT>
+// Offsets of one column of a column pass: element y at base + y step (ft:
+// the field's tile width or 0).
 struct ColField {
   uint32_t base, step;
   __device__ __forceinline__ ColField(uint32_t x, int W, int H, int ft) {
     if (ft) {
-      base = (x / CT) * (uint32_t)H * CT + x % CT;
-      step = CT;
+      const uint32_t l = __builtin_ctz(ft);
+      base = ((x >> l) * (uint32_t)H << l) + (x & (ft - 1));
+      step = ft;
     } else {
       base = x;
       step = (uint32_t)W;
@@ -701,7 +702,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  const ColField<C::C> f(x, a.W, N, a.ft);
+  const ColField f(x, a.W, N, a.ft);
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.field, f.at(y)); });
   float tgt[P::REGS];
   const uint32_t tbase = (uint32_t)tile * N * C::C + c;
@@ -884,7 +885,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(AsColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  const ColField<C::C> f(x, a.W, N, a.ft);
+  const ColField f(x, a.W, N, a.ft);
   for_layout<L0>(t, [&](int s, int y) { v[s] = ldg_field<N>(a.io, f.at(y)); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;

@@ -3,8 +3,8 @@
 // A row pass gives every row (length W, the contiguous axis) to a team of T
 // threads and packs TEAMS rows into one workgroup.  FT is the column tile
 // width of the tiled field layout the GS-family row kernels of that length
-// take (0: row order only; a plan is tiled when its column pass has the same
-// tile width).  A column pass gives every
+// take (0: row order only; a plan is tiled when its column pass's tile width
+// divides FT).  A column pass gives every
 // column (length H) to a team and packs C adjacent columns into one
 // workgroup, so each global access covers C * 8 contiguous bytes per row.
 // Teams of at most 64 threads that do not straddle a wavefront exchange data
@@ -37,10 +37,11 @@ template <int N> struct ColCfg;
 // The shapes of lengths 512, 1024, 1080, 1920 and 2048 were chosen by timing
 // the GS loop on MI355X over candidate team sizes, radix orders and column
 // tile widths (single holograms and same-shape batches); the rest are
-// untuned defaults.  The tiled GS layout (FT) measured 5 % faster per 1024^2
-// iteration and level at 2048^2; at 1920 x 1080 (column tiles of 8, row
-// kernels of 1920 compiled for 4) and for rows of 64-thread teams, which
-// cannot interleave, row order is kept.  Wider column tiles (C = 8: 64-byte row segments) win
+// untuned defaults.  The tiled GS layout took a 1024^2 iteration from 21.8
+// to 20.1 us with tiles of 8 (4: 20.6, 16: 22.1) and is level at 2048^2
+// (tiles of 8; 16 is 1 % slower); rows of 64-thread teams cannot interleave
+// and keep row order, and so does 1920 x 1080, where tiles measured 3-6 %
+// slower.  Wider column tiles (C = 8: 64-byte row segments) win
 // where the frame still gives every CU a tile.
 //          N     rows/WG  T    FT  radices
 HG_ROW_CFG(16,    64,     4,  0,   4, 4)
@@ -49,7 +50,7 @@ HG_ROW_CFG(64,    32,     8,  0,   8, 8)
 HG_ROW_CFG(128,   16,    16,  0,   8, 2, 8)
 HG_ROW_CFG(256,   16,    16,  0,   16, 16)
 HG_ROW_CFG(512,   2,    64,  0,   8, 8, 8)
-HG_ROW_CFG(1024,   2,   128,  4,   8, 4, 4, 8)
+HG_ROW_CFG(1024,   2,   128,  8,   8, 4, 4, 8)
 HG_ROW_CFG(2048,   2,   128,  8,   16, 8, 16)
 HG_ROW_CFG(4096,   2,   128,  0,   16, 16, 16)
 HG_ROW_CFG(24,    32,     8,  0,   8, 3)
