@@ -97,6 +97,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->col.ospr_b, e->col.lds));
   chk(allow_lds(e->col.ospr_b_pair, e->col.lds));
   chk(allow_lds(e->row.grad_row, e->row.lds));
+  chk(allow_lds(e->row.grad_row_next, e->row.lds));
   chk(allow_lds(e->col.grad_col, e->col.lds));
   chk(allow_lds(e->row.as_row, e->row.lds));
   chk(allow_lds(e->row.as_row_nmse, e->row.lds));
@@ -473,6 +474,9 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
   };
   const int states = steps + (final_loss ? 1 : 0);
   int chunk0 = 0;
+  // true when the field already holds the forward row pass of the plane about
+  // to be evaluated (made by the previous adjoint row pass)
+  bool started = false;
   for (int k = 0; k < states; ++k) {
     const bool is_step = k < steps;
     if (is_step && m) {
@@ -481,8 +485,11 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
       ga.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
     }
     for (int j = 0; j < P; ++j) {
-      plane_chirp(j, fa.q1y, fa.q1x);
-      hipLaunchKernelGGL(rk.gs_start, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, fa);
+      if (!started) {
+        plane_chirp(j, fa.q1y, fa.q1x);
+        hipLaunchKernelGGL(rk.gs_start, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, fa);
+      }
+      started = false;
       ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
       ca.sc = sc + j;
       ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * p0->col_blocks : nullptr;
@@ -491,7 +498,16 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
         plane_chirp(j, ga.q1y, ga.q1x);
         ga.first = j == 0;
         ga.last = j == P - 1;
-        hipLaunchKernelGGL(rk.grad_row, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+        // the next evaluation: plane j + 1 of this state, else plane 0 of the
+        // next state (the phase this pass leaves: updated by Adam, or as it was)
+        const int nj = j + 1 < P ? j + 1 : (k + 1 < states ? 0 : -1);
+        if (nj >= 0) {
+          plane_chirp(nj, ga.qny, ga.qnx);
+          hipLaunchKernelGGL(rk.grad_row_next, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+          started = true;
+        } else {
+          hipLaunchKernelGGL(rk.grad_row, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+        }
       } else if (loss) {
         hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p0->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
       }

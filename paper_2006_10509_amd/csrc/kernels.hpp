@@ -364,6 +364,25 @@ struct RowTable {
   }
 };
 
+// A second per-column table of a row pass (the next plane's chirp in the
+// gradient row pass): registers when they fit, else read from global memory
+// where it is used (the LDS table region holds the first table).
+template <int N, class L>
+struct RowTableDirect {
+  using P = typename RowCfg<N>::P;
+  static constexpr bool IN_REGS = P::REGS <= 16;
+  float2 r[IN_REGS ? P::REGS : 1];
+  const float2* src;
+  __device__ __forceinline__ void begin(const float2* s, int t) {
+    src = s;
+    if constexpr (IN_REGS) for_layout<L>(t, [&](int i, int x) { r[i] = s[x]; });
+  }
+  __device__ __forceinline__ float2 at(int i, int x) const {
+    if constexpr (IN_REGS) return r[i];
+    else return src[x];
+  }
+};
+
 // ===========================================================================
 // Propagation passes: out = post * Sh_out(FFT2(Sh_in(pre * in))), separable
 // pre/post tables and cyclic shifts (Fourier: none; Fresnel: chirps + centring).
@@ -747,7 +766,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
 // Gradient-descent hologram optimisation: adjoint row pass
 // ===========================================================================
 struct GradRowArgs {
-  const float2* field;     // output of the COL_GRAD pass of this plane
+  float2* field;           // in: output of the COL_GRAD pass of this plane;
+                           // out (NEXT): forward row pass of the next plane
   int ft;                  // its layout (RowField)
   float* phase;            // SLM phase phi [H][W]; updated in place by the Adam step
   int H;
@@ -760,6 +780,8 @@ struct GradRowArgs {
   float* v;
   float lr, beta1, beta2, eps;
   float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
+  const float2* qny;       // NEXT: source chirp of the next plane; null -> Fourier plane
+  const float2* qnx;
   const float2* tw;
   const float2* twr;
 };
@@ -768,14 +790,20 @@ struct GradRowArgs {
 // exp(i phi) recomputed from phi rather than stored -> g = 2 Im(conj(V) G)
 // added to the sum over planes; after the last plane the sum is written out
 // and/or one Adam step updates phi.  The accumulator, moments and phase are
-// loaded with the field, before the transform.
-template <int N>
+// loaded with the field, before the transform.  NEXT: the same pass then
+// starts the next forward evaluation from the phase it holds (the next plane,
+// or after the last plane the next state's first plane, from the updated
+// phase): Q1' exp(i phi) -> row FFT -> field, the arithmetic of
+// k_gs_row_start on a continuous phase, so the gradient method needs no
+// separate start pass after its first.
+template <int N, bool NEXT>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
   using LL = RowLds<N>;
   using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
-  using LF = Layout<P, false, false>;  // its last stage
+  using LF = Layout<P, false, false>;  // its last stage == first of the forward run
+  using L1 = Layout<P, false, true>;   // last stage of the forward run
   const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
@@ -792,17 +820,25 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
     vv[s] = adam ? ldg_f<N>(a.v, row + x) : 0.0f;
   });
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, false, true>;
+  using TW = PassTwiddles<P, C::THREADS, NEXT, true>;
   using QX = RowTable<N, LF>;
+  using QN = RowTableDirect<N, LF>;
   TW tw;
   QX qx;
+  QN qn;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   const bool fres = a.q1y != nullptr;
+  const bool nfres = NEXT && a.qny != nullptr;
   if (fres) qx.begin(a.q1x, t);
+  if (nfres) qn.begin(a.qnx, t);
   if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
-  if (!rt.live) return;   // no barrier follows
+  const float2 qny = nfres ? a.qny[rt.y] : make_float2(1.f, 0.f);
+  if constexpr (!NEXT) {
+    if (!rt.live) return;   // no barrier follows
+  }
+  const bool live = rt.live;
   for_layout<LF>(t, [&](int s, int x) {
     const uint32_t i = row + x;
     float sn, cs;
@@ -812,18 +848,31 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
     const float2 G = v[s];
     const float g = fmaf(2.0f, fmaf(V.x, G.y, -(V.y * G.x)), ac[s]);
     if (!a.last) {
-      stg_f<N>(a.acc, i, g);
-      return;
+      if (live) stg_f<N>(a.acc, i, g);
+    } else {
+      if (a.grad_out && live) stg_f<N>(a.grad_out, i, g);
+      if (adam) {
+        const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g);
+        const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g * g);
+        const float phn = ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps);
+        if (live) {
+          stg_f<N>(a.m, i, m1);
+          stg_f<N>(a.v, i, v1);
+          stg_f<N>(a.phase, i, phn);
+        }
+        if constexpr (NEXT) sincosf(phn, &sn, &cs);
+      }
     }
-    if (a.grad_out) stg_f<N>(a.grad_out, i, g);
-    if (adam) {
-      const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g);
-      const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g * g);
-      stg_f<N>(a.m, i, m1);
-      stg_f<N>(a.v, i, v1);
-      stg_f<N>(a.phase, i, ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps));
+    if constexpr (NEXT) {
+      float2 h = make_float2(cs, sn);
+      if (nfres) h = cmul(h, cmul(qny, qn.at(s, x)));
+      v[s] = h;
     }
   });
+  if constexpr (NEXT) {
+    tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+    if (live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, f.at(x), v[s]); });
+  }
 }
 
 // ===========================================================================
@@ -1121,6 +1170,7 @@ struct RowKernels {
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
   void (*grad_row)(GradRowArgs);
+  void (*grad_row_next)(GradRowArgs);   // ... then the next forward row pass
   void (*as_row)(AsRowArgs);
   void (*as_row_nmse)(AsRowArgs);
   int teams, threads;
@@ -1177,7 +1227,8 @@ LengthEntry make_length_entry() {
   e.row.gs_row_general = k_gs_row<N, -1, false>;
   e.row.ospr_a = k_ospr_a<N>;
   e.row.ospr_c = k_ospr_c<N>;
-  e.row.grad_row = k_grad_row<N>;
+  e.row.grad_row = k_grad_row<N, false>;
+  e.row.grad_row_next = k_grad_row<N, true>;
   e.row.as_row = k_as_row<N, true>;
   e.row.as_row_nmse = k_as_row<N, false>;
   e.row.teams = RowCfg<N>::TEAMS;
