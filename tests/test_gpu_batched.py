@@ -54,6 +54,8 @@ def run_single(plan, target, phase, iters, illum=None):
     (1080, 1920, 2, 4, False, 3),
     (120, 90, 4, 0, True, 7),
     (2048, 2048, 2, 4, False, 2),
+    (1024, 1024, 3, 8, True, 3),
+    (1080, 1024, 2, 4, False, 2),
 ])
 def test_batched_equals_single_calls_bitwise(h, w, batch, levels, fresnel, iters):
     print(f"batched {batch} x {h}x{w} L={levels} fresnel={fresnel} it={iters}", flush=True)

@@ -7,9 +7,11 @@ Quantised levels are compared state by state (the GPU run one iteration at a
 time, which is bitwise the same as one call): every state must match the
 oracle's except at pixels whose quantised angle lies within 1e-5 rad of a
 level boundary.  Quantised GS is chaotic at such ties: one pixel that rounds
-the other way changes a few hundred levels one iteration later at 1024^2, so
-after the first in-band difference the two trajectories are legitimately
-different and only the NMSE is compared further."""
+the other way changes a few hundred levels one iteration later at 1024^2, and
+the NMSE of the two trajectories then drifts apart too.  So at the first
+in-band difference the oracle is restarted from the GPU's state (its level
+map, which the quantiser maps to itself) and the comparison of levels and
+NMSE continues against that run, segment by segment."""
 import hashlib
 import json
 import os
@@ -64,42 +66,52 @@ def gpu_level_states(plan, target, phi0, iters, illum=None):
     return states
 
 
-def compare_states(gpu_states, ref_trace, levels):
-    """First state whose levels differ (None if none); asserts that every
-    difference in that state lies inside the boundary band."""
-    for k, (g, r) in enumerate(zip(gpu_states, ref_trace)):
-        diff = g != r["levels"]
-        if diff.any():
-            band = boundary_distance(r["angle"], levels) < 1e-5
-            outside = int((diff & ~band).sum())
-            assert outside == 0, f"state {k}: {outside} level differences outside the boundary band"
-            return k
-    return None
+def check_quantised_segments(target, phi0, iters, levels, fres, illum, nm, states):
+    """Levels and NMSE of every GPU state against the oracle, restarting the
+    oracle from the GPU's state at each in-band difference.  Returns the
+    states at which it was restarted."""
+    restarts = []
+    k0, start = 0, phi0
+    while True:
+        ref = oracle.gs_iterate(target, start, iters - k0, levels=levels, illumination=illum, fresnel=fres, trace=True)
+        diverged = None
+        for k in range(k0, iters + 1):
+            r = ref["trace"][k - k0]
+            e = ref["nmse"][k - k0]
+            assert abs(nm[k] - e) <= NMSE_TOL * e, (k, nm[k], e)
+            diff = states[k] != r["levels"]
+            if diff.any():
+                band = boundary_distance(r["angle"], levels) < 1e-5
+                outside = int((diff & ~band).sum())
+                assert outside == 0, f"state {k}: {outside} level differences outside the boundary band"
+                diverged = k
+                break
+        if diverged is None or diverged == iters:
+            return restarts
+        assert not restarts or diverged > restarts[-1], "restarted oracle differs from its own start state"
+        restarts.append(diverged)
+        k0 = diverged
+        start = states[diverged].astype(np.float64) * (2 * np.pi / levels)
 
 
 def check_against_oracle(h, w, target, phi0, iters, levels, fresnel, illum=None):
     plan = make_plan(h, w, levels, fresnel)
     phase, lev, nm = run_gs(plan, target, phi0, iters, illum)
-    ref = oracle.gs_iterate(target, phi0, iters, levels=levels, illumination=illum,
-                            fresnel=dict(wavelength=532e-9, pitch=8e-6, distance=0.5) if fresnel else None,
-                            trace=bool(levels))
-    rel = np.abs(nm - np.array(ref["nmse"])) / np.array(ref["nmse"])
-    assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
+    fres = dict(wavelength=532e-9, pitch=8e-6, distance=0.5) if fresnel else None
     if levels:
         states = gpu_level_states(plan, target, phi0, iters, illum)
         assert np.array_equal(states[-1], lev)
-        first = compare_states(states, ref["trace"], levels)
-        frac = float((lev != ref["levels"]).mean())
-        print(f"first in-band divergence at state {first}; final level mismatch fraction {frac:.2e}")
-        if first is None:
-            assert frac == 0.0
+        restarts = check_quantised_segments(target, phi0, iters, levels, fres, illum, nm, states)
+        print(f"oracle restarted at in-band divergences: states {restarts}")
         expect_phase = lev * (2 * np.pi / levels)
         assert np.allclose(phase, expect_phase.astype(np.float32), atol=1e-6)
-    else:
-        l2, frac = phase_parity(phase, ref["phase"])
-        assert l2 <= 1e-4 and frac <= 1e-4, (l2, frac)
-        assert (phase >= 0).all() and (phase < 2 * np.pi).all()
-    return nm, ref
+        return
+    ref = oracle.gs_iterate(target, phi0, iters, levels=levels, illumination=illum, fresnel=fres)
+    rel = np.abs(nm - np.array(ref["nmse"])) / np.array(ref["nmse"])
+    assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
+    l2, frac = phase_parity(phase, ref["phase"])
+    assert l2 <= 1e-4 and frac <= 1e-4, (l2, frac)
+    assert (phase >= 0).all() and (phase < 2 * np.pi).all()
 
 
 def test_gs_fourier_256_continuous_20_iterations():
@@ -159,6 +171,10 @@ def test_gs_fresnel_1024_L8_first_10_iterations():
     (512, 128, 2, True, 10),
     (2048, 2048, 8, True, 2),
     (4096, 16, 16, False, 5),
+    # tiled field layout (rows of 1024 or 2048) under other column lengths
+    (1080, 1024, 8, True, 3),
+    (1024, 2048, 4, False, 2),
+    (4096, 1024, 0, False, 1),
 ])
 def test_gs_shapes_and_modes(h, w, levels, fresnel, iters):
     print(f"gs {h}x{w} L={levels} fresnel={fresnel} it={iters}", flush=True)
