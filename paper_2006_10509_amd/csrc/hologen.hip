@@ -908,6 +908,7 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, w.sc, stream);
 
   OsprRowArgs ra{};
+  ra.ft = p->ft;
   ra.field = w.field;
   ra.H = H;
   ra.target = target_amp;
@@ -917,6 +918,7 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   ra.tw = p->tw_row[0];
   ra.twr = p->tw_row[1];
   OsprColArgs ca{};
+  ca.ft = p->ft;
   ca.field = w.field;
   ca.W = W;
   ca.tw = p->tw_col[0];
@@ -953,6 +955,7 @@ hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_pha
   if (nmse) enqueue_stats(p, w, target_amp, nullptr, (double)n * (double)n, w.sc, stream);
 
   OsprRowArgs ra{};
+  ra.ft = p->ft;
   ra.field = w.field;
   ra.H = H;
   ra.target = target_amp;
@@ -961,6 +964,7 @@ hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_pha
   ra.tw = p->tw_row[0];
   ra.twr = p->tw_row[1];
   OsprColArgs ca{};
+  ca.ft = p->ft;
   ca.field = w.field;
   ca.W = W;
   ca.tw = p->tw_col[0];

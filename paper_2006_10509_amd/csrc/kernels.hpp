@@ -216,7 +216,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 
 // ---------------------------------------------------------------------------
 // Field layout of the Gerchberg-Saxton family (GS, multi-plane GS, gradient,
-// angular-spectrum GS) between its row and column passes, chosen per plan:
+// angular-spectrum GS) and of OSPR between their row and column passes,
+// chosen per plan:
 //   ft = 0: row order, element (y, x) at y W + x;
 //   ft > 0: column tiles of ft (a power of two and a multiple of the column
 //           pass's tile width), stored one tile after another, each row by
@@ -227,7 +228,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // workgroup interleaves its rows across the lanes (RowTeam) moves whole
 // lines.  A row kernel of length N is compiled for one tile width,
 // RowTeam<RowCfg<N>>::FT (0: row order only); a plan is tiled when that
-// width is a multiple of its column pass's.  Propagation, OSPR and the
+// width is a multiple of its column pass's.  Propagation and the
 // single-pixel search keep row order.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr uint32_t field_width(uint32_t w, uint32_t ft) { return ft ? (w + ft - 1) / ft * ft : w; }
@@ -244,7 +245,8 @@ struct RowTeam {
   // register slot must lie a multiple of FT from t.
   static constexpr int FT = C::FT;
   static_assert(FT == 0 || (!C::WAVE_SYNC && C::TEAMS > 1 && (FT & (FT - 1)) == 0 && P::T % FT == 0 &&
-                            Layout<P, true, false>::STRIDE % FT == 0 && Layout<P, false, true>::STRIDE % FT == 0),
+                            Layout<P, true, false>::STRIDE % FT == 0 && Layout<P, false, true>::STRIDE % FT == 0 &&
+                            Layout<P, false, false>::STRIDE % FT == 0),
                 "tile width unusable with this row shape");
   int t, team, y;
   bool live;
@@ -1014,6 +1016,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row(AsRowArgs a) {
 struct OsprRowArgs {
   float2* field;
   int H;
+  int ft;                  // field layout between the passes (RowField)
   const float* target;     // centred amplitude [H][W]
   const float* theta;      // centred subframe phase [H][W] (pass A)
   float* intensity;        // centred accumulator / output [H][W] (pass C)
@@ -1033,7 +1036,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
   using LL = RowLds<N>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
@@ -1055,13 +1058,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_a(OsprRowArgs a) {
     v[s] = make_float2(am[s] * cs, am[s] * sn);
   });
   tw.template run<false, +1, C::WAVE_SYNC>(v, t, lds);
-  const uint32_t row = (uint32_t)rt.y * N;
-  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, row + x, v[s]); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, f.at(x), v[s]); });
 }
 
 struct OsprColArgs {
   float2* field;
   int W;
+  int ft;              // field layout between the passes (ColField)
   uint8_t* levels;     // [H][W] of this subframe, natural SLM order; may be null
   uint8_t* levels_im;  // pairs: [H][W] of the subframe binarised from Im G; may be null
   const float2* tw;
@@ -1086,7 +1090,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   const uint32_t x = live ? col : a.W - 1;
   LdsView<C::C> lds{hg_dyn_lds + c};
   float2 v[P::REGS];
-  for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, (uint32_t)y * a.W + x); });
+  const ColField f(x, a.W, N, a.ft);
+  for_layout<LI>(t, [&](int s, int y) { v[s] = ldg(a.field, f.at(y)); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;
   TW tw;
@@ -1107,7 +1112,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
     v[s] = make_float2(neg ? -1.0f : 1.0f, im);
   });
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, (uint32_t)y * a.W + x, v[s]); });
+  if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, f.at(y), v[s]); });
 }
 
 // Pass C: row FFT -> |.|^2 -> accumulate into the centred intensity (fftshift on
@@ -1120,12 +1125,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   __shared__ float red[C::THREADS / 64];
-  const RowTeam<C> rt(a.H);
+  const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
-  const uint32_t row = (uint32_t)rt.y * N;
-  for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, row + x); });
+  const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
+  for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
   const uint32_t orow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
   const bool nm = a.last && a.partials;
   float prev[P::REGS], tg[P::REGS];
