@@ -628,13 +628,24 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   const bool fres = GENERAL ? (a.q1y != nullptr) : FRES;
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
   for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
+  // general pass: the illumination and an outgoing chirp are loaded with the
+  // field, not where they are used after the transform
+  float ill[GENERAL ? P::REGS : 1];
+  if constexpr (GENERAL) {
+    if (a.illum) for_layout<LF>(t, [&](int s, int x) { ill[s] = ldg(a.illum, row + x); });
+  }
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, true>;
   using QX = RowTable<N, LF>;
+  using QO = RowTableDirect<N, LF>;
   TW tw;
   QX qx;
+  QO qo;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if (fres) qx.begin(a.q1x, t);
+  if constexpr (GENERAL) {
+    if (a.q_out_set && a.qoy) qo.begin(a.qox, t);
+  }
   if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
@@ -665,8 +676,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       int level;
       float2 u = slm_constrain_rt(g, a.slm, level);
       if (out) write_state(a, row + x, u, level);
-      if (a.illum) u = cscale(u, ldg(a.illum, row + x));
-      if (a.q_out_set && fres_out) q = cmul(qoy, ldg(a.qox, (uint32_t)x));
+      if (a.illum) u = cscale(u, ill[s]);
+      if (a.q_out_set && fres_out) q = cmul(qoy, qo.at(s, x));
       v[s] = fres_out ? cmul(u, q) : u;
     });
   }
