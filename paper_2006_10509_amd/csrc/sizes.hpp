@@ -58,7 +58,7 @@ HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)
 HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
 HG_ROW_CFG(120,   16,    16,  0,   8, 3, 5)
 HG_ROW_CFG(1080,   4,    64,  0,   8, 3, 3, 3, 5)
-HG_ROW_CFG(1920,   2,   128,  0,   16, 8, 3, 5)
+HG_ROW_CFG(1920,   4,   128,  0,   16, 8, 3, 5)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
