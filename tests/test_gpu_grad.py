@@ -116,6 +116,26 @@ def test_adam_trajectory_matches_oracle(h, w, distances):
     assert loss[-1] < 0.5 * loss[0]
 
 
+def test_adam_on_the_tiled_layout_matches_oracle_and_resumes():
+    """1024^2 plans hold the field in column tiles; the adjoint row pass of
+    the last plane also starts the next step's first plane from the updated
+    phase.  Loss curve against the oracle, and 2 + 2 steps bitwise equal to 4."""
+    h = w = 1024
+    print("adam 1024x1024 planes=[0.45, 0.5] tiled", flush=True)
+    planes, dicts = make_planes(h, w, [0.45, 0.5])
+    targets, phi = problem(h, w, 2, 77)
+    steps = 4
+    ph, mm, vv, loss = run_adam(planes, targets, phi, steps)
+    ref = oracle.grad_descent(phi.astype(np.float64), list(targets.astype(np.float64)), dicts, steps, lr=0.05)
+    rel = np.abs(loss - np.array(ref["loss"])) / np.array(ref["loss"])
+    assert rel.max() <= 1e-3, (rel.max(), int(rel.argmax()))
+    ph1, m1, v1, loss1 = run_adam(planes, targets, phi, 2)
+    ph2, m2, v2, loss2 = run_adam(planes, targets, host(ph1), 2, first=3, m=m1, v=v1)
+    assert np.array_equal(host(ph), host(ph2))
+    assert np.array_equal(host(mm), host(m2)) and np.array_equal(host(vv), host(v2))
+    assert np.array_equal(loss[:3], loss1) and np.array_equal(loss[2:], loss2)
+
+
 def test_adam_resumes_bitwise_across_calls():
     planes, _ = make_planes(128, 128, [0.5, 0.45])
     targets, phi = problem(128, 128, 2, 21)
