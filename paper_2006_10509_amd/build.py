@@ -33,8 +33,8 @@ def hipcc() -> str:
     return path
 
 
-def lengths() -> list:
-    text = open(os.path.join(CSRC, "sizes.hpp")).read()
+def lengths(csrc: str = CSRC) -> list:
+    text = open(os.path.join(csrc, "sizes.hpp")).read()
     block = text[text.index("#define HG_FOR_EACH_LENGTH"):]
     block = block[:block.index("\n\n")]
     return [int(n) for n in re.findall(r"X\((\d+)\)", block)]
@@ -53,23 +53,29 @@ def _run(cmd):
     return proc.stderr
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    t0 = time.time()
+def build_library(csrc: str, out: str, jobs: int = 0) -> str:
+    """Compile the sources in csrc (the lengths its sizes.hpp lists) into out."""
     jobs = jobs or min(16, os.cpu_count() or 4)
     with tempfile.TemporaryDirectory(prefix="hg_build_") as tmp:
         jobs_list = []
-        for n in lengths():
+        for n in lengths(csrc):
             obj = os.path.join(tmp, f"len_{n}.o")
             jobs_list.append([hipcc(), *common_flags(), f"-DHG_LEN={n}", "-c",
-                              os.path.join(CSRC, "length.hip"), "-o", obj])
+                              os.path.join(csrc, "length.hip"), "-o", obj])
         host_obj = os.path.join(tmp, "hologen.o")
-        jobs_list.append([hipcc(), *common_flags(), "-c", os.path.join(CSRC, "hologen.hip"), "-o", host_obj])
+        jobs_list.append([hipcc(), *common_flags(), "-c", os.path.join(csrc, "hologen.hip"), "-o", host_obj])
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             list(ex.map(_run, jobs_list))
         objs = [j[-1] for j in jobs_list]
-        out_tmp = LIB + ".tmp"
+        out_tmp = out + ".tmp"
         _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp])
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, out)
+    return out
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    t0 = time.time()
+    build_library(CSRC, LIB, jobs)
     if verbose:
         print(f"built {LIB} ({len(lengths())} transform lengths) in {time.time() - t0:.1f} s")
     return LIB

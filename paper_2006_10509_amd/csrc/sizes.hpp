@@ -36,8 +36,9 @@ template <int N> struct ColCfg;
 
 // The shapes of lengths 512, 1024, 1080, 1920 and 2048 were chosen by timing
 // the GS loop on MI355X over candidate team sizes, radix orders and column
-// tile widths (single holograms and same-shape batches); the rest are
-// untuned defaults.  The tiled GS layout took a 1024^2 iteration from 21.8
+// tile widths (single holograms and same-shape batches; paper_2006_10509_amd/
+// autotune.py automates the search); the rest are untuned defaults.
+// The tiled GS layout took a 1024^2 iteration from 21.8
 // to 20.1 us with tiles of 8 (4: 20.6, 16: 22.1) and is level at 2048^2
 // (tiles of 8; 16 is 1 % slower); rows of 64-thread teams cannot interleave
 // and keep row order, and so does 1920 x 1080, where tiles measured 3-6 %
@@ -58,7 +59,7 @@ HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)
 HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
 HG_ROW_CFG(120,   16,    16,  0,   8, 3, 5)
 HG_ROW_CFG(1080,   4,    64,  0,   8, 3, 3, 3, 5)
-HG_ROW_CFG(1920,   4,   128,  0,   16, 8, 3, 5)
+HG_ROW_CFG(1920,   4,   128,  0,   16, 3, 5, 8)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
