@@ -27,7 +27,11 @@ constants of the kernels (template arguments), so the tuner works ahead of
 time rather than inside the library.
 
     python -m paper_2006_10509_amd.autotune --shape 1080x1920 [--shape ...]
-        [--max-candidates 6] [--cache PATH] [--apply]
+        [--batch B] [--max-candidates 6] [--cache PATH] [--apply]
+
+--batch B times B same-shape holograms per launch (hg_gs_iterate_batched)
+and ranks by time per hologram-iteration: small frames that run in batches
+tune differently from a single hologram, which is latency-bound.
 
 Needs hipcc for the variant builds and a GPU for the timing, which runs in a
 child process per candidate (`--measure LIB HxW`).
@@ -156,7 +160,7 @@ def col_shapes(n: int, cur: ColCfg, limit: int) -> List[ColCfg]:
 # ---------------------------------------------------------------------------
 # measurement (child process)
 # ---------------------------------------------------------------------------
-def measure(lib: str, h: int, w: int) -> dict:
+def measure(lib: str, h: int, w: int, batch: int = 1) -> dict:
     sys.path.insert(0, hb.ROOT)
     from paper_2006_10509_amd import hologen as hg
     hg.LIB_PATH = os.path.abspath(lib)
@@ -168,16 +172,23 @@ def measure(lib: str, h: int, w: int) -> dict:
     phase = torch.from_numpy(p).cuda()
     ws = plan.workspace()
     iters, calls = 50, 5
-    hg.hg_gs_iterate(plan, target, phase, iters, ws)
+    if batch > 1:
+        target_b = target.expand(batch, h, w).contiguous()
+        phase_b = phase.expand(batch, h, w).contiguous()
+        ws_b = torch.empty(hg.workspace_bytes_batched(plan, batch), dtype=torch.uint8, device="cuda")
+        run = lambda: hg.hg_gs_iterate_batched(plan, target_b, phase_b, iters, ws_b)  # noqa: E731
+    else:
+        run = lambda: hg.hg_gs_iterate(plan, target, phase, iters, ws)  # noqa: E731
+    run()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(calls):
-        hg.hg_gs_iterate(plan, target, phase, iters, ws)
+        run()
     b.record()
     b.synchronize()
-    us = a.elapsed_time(b) * 1e3 / (iters * calls)
+    us = a.elapsed_time(b) * 1e3 / (iters * calls * batch)
     # results check: three continuous-phase iterations from the same start
     cplan = hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_PHASE, 0)
     nm = torch.zeros(4, dtype=torch.float32, device="cuda")
@@ -189,7 +200,8 @@ def measure(lib: str, h: int, w: int) -> dict:
 # tuner (parent process: builds on the CPU, one child per timing)
 # ---------------------------------------------------------------------------
 class Tuner:
-    def __init__(self, cache_path: str, jobs: int, verbose: bool = True):
+    def __init__(self, cache_path: str, jobs: int, batch: int = 1, verbose: bool = True):
+        self.batch = batch
         self.cache_path = cache_path
         self.cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
         self.jobs = jobs
@@ -203,7 +215,7 @@ class Tuner:
             print(*a, flush=True)
 
     def key(self, h, w, row: RowCfg, col: ColCfg) -> str:
-        return f"{self.gpu}|{h}x{w}|{row_line(w, row)}|{col_line(h, col)}"
+        return f"{self.gpu}|{h}x{w}x{self.batch}|{row_line(w, row)}|{col_line(h, col)}"
 
     def _build(self, tmp: str, h: int, w: int, row: RowCfg, col: ColCfg) -> Optional[str]:
         src = os.path.join(tmp, "csrc")
@@ -219,7 +231,8 @@ class Tuner:
         return out
 
     def _time(self, lib: str, h: int, w: int) -> Optional[dict]:
-        cmd = [sys.executable, "-m", "paper_2006_10509_amd.autotune", "--measure", lib, f"{h}x{w}"]
+        cmd = [sys.executable, "-m", "paper_2006_10509_amd.autotune", "--measure", lib, f"{h}x{w}",
+               "--batch", str(self.batch)]
         try:
             proc = subprocess.run(cmd, capture_output=True, text=True, timeout=300, cwd=hb.ROOT)
         except subprocess.TimeoutExpired:
@@ -258,7 +271,7 @@ class Tuner:
                     us, note = None, "rejected (results differ from the current build)"
                 self.cache[self.key(h, w, r, c)] = us
                 self.log(f"  {row_line(w, r):44s} {col_line(h, c):40s} "
-                         f"{'%.2f us/it' % us if us else note}")
+                         f"{'%.2f us/hologram-iteration' % us if us else note}")
                 json.dump(self.cache, open(self.cache_path, "w"), indent=1, sort_keys=True)
         out = []
         for r, c in cands:
@@ -302,6 +315,7 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--shape", action="append", default=[], help="frame shape HxW (repeatable)")
     ap.add_argument("--max-candidates", type=int, default=6, help="candidates per round")
+    ap.add_argument("--batch", type=int, default=1, help="holograms per launch while timing")
     ap.add_argument("--cache", default=os.path.join(os.path.expanduser("~"), ".cache", "hologen_tune.json"))
     ap.add_argument("--jobs", type=int, default=4, help="variant builds in parallel")
     ap.add_argument("--apply", action="store_true", help="write the winners into csrc/sizes.hpp")
@@ -309,18 +323,19 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.measure:
         h, w = (int(v) for v in a.measure[1].split("x"))
-        print(json.dumps(measure(a.measure[0], h, w)))
+        print(json.dumps(measure(a.measure[0], h, w, a.batch)))
         return 0
     if not a.shape:
         ap.error("give at least one --shape HxW")
     os.makedirs(os.path.dirname(os.path.abspath(a.cache)), exist_ok=True)
-    tuner = Tuner(a.cache, a.jobs)
+    tuner = Tuner(a.cache, a.jobs, a.batch)
     rows, cols = {}, {}
     for s in a.shape:
         h, w = (int(v) for v in s.split("x"))
         t0 = time.time()
         row, col, start, best = tuner.tune(h, w, a.max_candidates)
-        print(f"{h}x{w}: {start:.2f} -> {best:.2f} us per iteration ({time.time() - t0:.0f} s)")
+        print(f"{h}x{w} (batch {a.batch}): {start:.2f} -> {best:.2f} us per hologram-iteration "
+              f"({time.time() - t0:.0f} s)")
         print("  " + row_line(w, row))
         print("  " + col_line(h, col))
         rows[w], cols[h] = row, col
