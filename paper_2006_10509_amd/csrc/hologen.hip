@@ -90,6 +90,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->row.gs_row_general, e->row.lds));
   chk(allow_lds(e->row.ospr_a, e->row.lds));
   chk(allow_lds(e->row.ospr_c, e->row.lds));
+  chk(allow_lds(e->row.ospr_ca, e->row.lds));
   chk(allow_lds(e->col.prop_fwd, e->col.lds));
   chk(allow_lds(e->col.prop_inv, e->col.lds));
   chk(allow_lds(e->col.gs_col, e->col.lds));
@@ -923,15 +924,17 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
   ca.W = W;
   ca.tw = p->tw_col[0];
   ca.twr = p->tw_col[1];
+  // pass A of subframe 0; after that each pass C also runs the next pass A
+  ra.theta = sub_phase;
+  launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
   for (int s = 0; s < n_sub; ++s) {
-    ra.theta = sub_phase + (size_t)s * n;
     ra.first = s == 0;
     ra.last = s == n_sub - 1;
     ra.partials = (ra.last && nmse) ? w.partials : nullptr;
+    ra.theta_next = ra.last ? nullptr : sub_phase + (size_t)(s + 1) * n;
     ca.levels = holograms ? holograms + (size_t)s * n : nullptr;
-    launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
     launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b, p->col_blocks, ck.threads, ck.lds, ca);
-    launch(p, HG_KERNEL_OSPR_C, stream, rk.ospr_c, p->row_blocks, rk.threads, rk.lds, ra);
+    launch(p, HG_KERNEL_OSPR_C, stream, ra.last ? rk.ospr_c : rk.ospr_ca, p->row_blocks, rk.threads, rk.lds, ra);
   }
   if (nmse)
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials,
@@ -969,16 +972,18 @@ hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_pha
   ca.W = W;
   ca.tw = p->tw_col[0];
   ca.twr = p->tw_col[1];
+  ra.theta = sub_phase;
+  launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
   for (int s = 0; s < n_pairs; ++s) {
-    ra.theta = sub_phase + (size_t)s * n;
+    const bool final_pair = s == n_pairs - 1;
     ra.first = s == 0;
     ra.last = 0;        // sums only: the finish kernel averages and scores
     ra.partials = nullptr;
+    ra.theta_next = final_pair ? nullptr : sub_phase + (size_t)(s + 1) * n;
     ca.levels = holograms ? holograms + (size_t)(2 * s) * n : nullptr;
     ca.levels_im = holograms ? holograms + (size_t)(2 * s + 1) * n : nullptr;
-    launch(p, HG_KERNEL_OSPR_A, stream, rk.ospr_a, p->row_blocks, rk.threads, rk.lds, ra);
     launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b_pair, p->col_blocks, ck.threads, ck.lds, ca);
-    launch(p, HG_KERNEL_OSPR_C, stream, rk.ospr_c, p->row_blocks, rk.threads, rk.lds, ra);
+    launch(p, HG_KERNEL_OSPR_C, stream, final_pair ? rk.ospr_c : rk.ospr_ca, p->row_blocks, rk.threads, rk.lds, ra);
   }
   // one partial per block: at most PAIR_MAX_BLOCKS, and never more than the
   // workspace's partial buffer holds (kNmseChunk x workgroups of a pass)

@@ -1030,6 +1030,7 @@ struct OsprRowArgs {
   int ft;                  // field layout between the passes (RowField)
   const float* target;     // centred amplitude [H][W]
   const float* theta;      // centred subframe phase [H][W] (pass A)
+  const float* theta_next; // pass C with NEXT: the next subframe's phase (its pass A)
   float* intensity;        // centred accumulator / output [H][W] (pass C)
   int first, last;
   float inv_nsub;
@@ -1128,7 +1129,10 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
 
 // Pass C: row FFT -> |.|^2 -> accumulate into the centred intensity (fftshift on
 // store); the last subframe scales by 1/N_sub and adds the NMSE partials.
-template <int N>
+// NEXT: the same rows then run pass A of the next subframe (T exp(i theta_next)
+// -> inverse row FFT -> field), so a subframe after the first costs two
+// passes; its phase and the target are loaded with the field.
+template <int N, bool NEXT>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
@@ -1150,6 +1154,15 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     prev[s] = a.first ? 0.0f : ldg(a.intensity, i);
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
+  float th[NEXT ? P::REGS : 1], am[NEXT ? P::REGS : 1];
+  if constexpr (NEXT) {
+    // pass A reads the input row y through ifftshift: source row y + H/2
+    for_layout<L0>(t, [&](int s, int x) {
+      const uint32_t i = orow + wrap_add<N>(x, N / 2);
+      th[s] = ldg(a.theta_next, i);
+      am[s] = ldg(a.target, i);
+    });
+  }
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, false>;
   TW tw;
@@ -1172,6 +1185,15 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     const float s = block_sum<C::THREADS>(rt.live ? acc : 0.0f, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
   }
+  if constexpr (NEXT) {
+    for_layout<L0>(t, [&](int s, int) {
+      float sn, cs;
+      sincosf(th[s], &sn, &cs);
+      v[s] = make_float2(am[s] * cs, am[s] * sn);
+    });
+    tw.template run<false, +1, C::WAVE_SYNC>(v, t, lds);
+    if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, f.at(x), v[s]); });
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,6 +1207,7 @@ struct RowKernels {
   void (*gs_row_general)(GsRowArgs); // outputs / illumination / any mode
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
+  void (*ospr_ca)(OsprRowArgs);   // pass C, then the next subframe's pass A
   void (*grad_row)(GradRowArgs);
   void (*grad_row_next)(GradRowArgs);   // ... then the next forward row pass
   void (*as_row)(AsRowArgs);
@@ -1242,7 +1265,8 @@ LengthEntry make_length_entry() {
   e.row.gs_row[4][1] = k_gs_row<N, GS_Q8, true>;
   e.row.gs_row_general = k_gs_row<N, -1, false>;
   e.row.ospr_a = k_ospr_a<N>;
-  e.row.ospr_c = k_ospr_c<N>;
+  e.row.ospr_c = k_ospr_c<N, false>;
+  e.row.ospr_ca = k_ospr_c<N, true>;
   e.row.grad_row = k_grad_row<N, false>;
   e.row.grad_row_next = k_grad_row<N, true>;
   e.row.as_row = k_as_row<N, true>;
