@@ -374,8 +374,8 @@ def main() -> int:
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part "
-              "of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
+              file=sys.stderr)
         return 2
 
     import numpy as np

@@ -49,7 +49,7 @@ typedef struct hg_plan_s* hg_plan;
 typedef enum {
   HG_OK = 0,
   HG_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad enum, non-finite optics, ... */
-  HG_ERR_UNSUPPORTED_SIZE = 2, /* a dimension this build has no transform for   */
+  HG_ERR_UNSUPPORTED_SIZE = 2, /* a dimension with no compiled transform        */
   HG_ERR_OUT_OF_MEMORY = 3,    /* plan tables could not be allocated            */
   HG_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed            */
   HG_ERR_INTERNAL = 5
@@ -87,7 +87,7 @@ hg_status hg_plan_destroy(hg_plan plan);
  * on this plan needs (a complex64 field plus reduction scratch).  0 for NULL. */
 size_t hg_workspace_bytes(hg_plan plan);
 
-/* 1 if this build compiles a transform of length n (usable as a width or a
+/* 1 if the library compiles a transform of length n (usable as a width or a
  * height), else 0. */
 int32_t hg_length_supported(int32_t n);
 

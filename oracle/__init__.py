@@ -31,8 +31,8 @@ step by step in the order the method performs it:
   search.py       single-pixel direct binary search and simulated annealing
                   (the paper's HoloGenAlgDSCuda / HoloGenAlgSACuda, Sec. 7.3).
 
-Readings taken where the paper is silent are listed in the design doc.  Every
-function is pinned by ``tests/test_oracle_*.py`` against closed forms,
+Where the paper is silent, each module's docstring states the reading it
+takes.  Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 brute-force sums, invariants and independent library routines.
 """
 from .dft import dft_naive, fft, ifft, fft2, ifft2, fftshift, ifftshift

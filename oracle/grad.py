@@ -2,8 +2,8 @@
 
 Test infrastructure only.  The paper names the algorithms its library holds
 and leaves further ones to future work (Sec. 8, Further Research and
-Conclusion); this module writes out the gradient method that the build adds,
-from its textbook definition, step by step:
+Conclusion); this module writes out the gradient method that the GPU library
+adds, from its textbook definition, step by step:
 
 Forward, per replay plane j (Fresnel source chirp Q1_j of distance z_j, or
 Q1 = 1 for a Fourier plane):

@@ -253,7 +253,7 @@ hg_status validate_desc(const hg_plan_desc* d) {
     if (n < 2 || n > 8192) return fail(HG_ERR_INVALID_ARGUMENT, "width/height must be in [2, 8192]");
     if (!smooth_235(n)) return fail(HG_ERR_UNSUPPORTED_SIZE, "width/height must be of the form 2^a 3^b 5^c");
     if (!find_length(n))
-      return fail(HG_ERR_UNSUPPORTED_SIZE, "no transform of length " + std::to_string(n) + " in this build");
+      return fail(HG_ERR_UNSUPPORTED_SIZE, "no transform of length " + std::to_string(n) + " is compiled into the library");
   }
   if (d->propagation != HG_FOURIER && d->propagation != HG_FRESNEL && d->propagation != HG_ANGULAR)
     return fail(HG_ERR_INVALID_ARGUMENT, "propagation must be HG_FOURIER, HG_FRESNEL or HG_ANGULAR");
