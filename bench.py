@@ -189,6 +189,40 @@ def mix_inputs(wl):
         return list(ex.map(_mix_inputs, wl.batched_mix()))
 
 
+def batched_1024(hg, wl, torch, stream, batch: int = 8, iterations: int = 50) -> dict:
+    """The headline workload's kernels with the GPU full: `batch` copies of
+    the 1024^2 Fresnel L = 8 problem in one hg_gs_iterate_batched call (NMSE
+    of every state), time per hologram-iteration and algorithmic GB/s at
+    36 B/px.  Context for the single-hologram roofline, not the metric."""
+    w = wl.GS_FRESNEL_1024
+    t, p = w.inputs()
+    plan = hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, w.distance, hg.HG_PHASE_QUANTISED,
+                   w.levels)
+    tb = torch.from_numpy(t).cuda().expand(batch, w.height, w.width).contiguous()
+    pb0 = torch.from_numpy(p).cuda().expand(batch, w.height, w.width).contiguous()
+    pb = pb0.clone()
+    nm = torch.empty((batch, iterations + 1), dtype=torch.float32, device="cuda")
+    ws = torch.empty(hg.workspace_bytes_batched(plan, batch), dtype=torch.uint8, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run():
+        pb.copy_(pb0)
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_gs_iterate_batched(plan, tb, pb, iterations, ws, nmse=nm, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    run()
+    ms = min(run() for _ in range(3))
+    us = ms * 1e3 / (iterations * batch)
+    gbs = sum(BYTES_PER_PX.values()) * w.height * w.width / (us * 1e-6) / 1e9
+    return {"workload": w.name, "holograms": batch, "iterations": iterations,
+            "us_per_hologram_iteration": round(us, 3), "iteration_gbs": round(gbs, 1),
+            "iteration_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def batched_mix(hg, wl, torch, stream, inputs, iterations: int = 50) -> dict:
     """The 64-hologram mixed batch (16 x 512^2, 24 x 1024^2, 16 x 2048^2,
     8 x 1080x1920; Fourier GS, 4 levels, 50 iterations, NMSE of every state):
@@ -463,11 +497,13 @@ def main() -> int:
         gb = grad_batch(hg, wl, torch, stream, args.grad_problems)
         log(f"  {gb}")
 
-    mix = None
+    mix = b1024 = None
     if not args.no_batched:
         log("mixed batch: 64 holograms, batched vs sequential")
         mix = batched_mix(hg, wl, torch, stream, mixed)
         log(f"  {mix}")
+        b1024 = batched_1024(hg, wl, torch, stream)
+        log(f"batched 1024^2: {b1024}")
 
     srch = pixel_search_1024(hg, wl, torch, stream)
     log(f"pixel search: {srch}")
@@ -490,7 +526,7 @@ def main() -> int:
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
                       "target_seed": w.target_seed, "phase_seed": w.phase_seed},
            "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
-           "batched_mix": mix, "ospr": osp, "pixel_search": srch,
+           "batched_mix": mix, "batched_1024": b1024, "ospr": osp, "pixel_search": srch,
            "rocfft_reference": rf}
     print(json.dumps(out), flush=True)
     return 0
