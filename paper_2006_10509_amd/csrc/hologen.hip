@@ -88,6 +88,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   for (auto& mode : e->row.gs_row)
     for (auto k : mode) chk(allow_lds(k, e->row.lds));
   chk(allow_lds(e->row.gs_row_general, e->row.lds));
+  for (auto k : e->row.gs_row_mp) chk(allow_lds(k, e->row.lds));
   chk(allow_lds(e->row.ospr_a, e->row.lds));
   chk(allow_lds(e->row.ospr_c, e->row.lds));
   chk(allow_lds(e->row.ospr_ca, e->row.lds));
@@ -1167,6 +1168,9 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
   ca.tw = p0->tw_col[0];
   ca.twr = p0->tw_col[1];
   const dim3 rows(p0->row_blocks), tiles(p0->col_blocks);
+  const int mp_mode = gs_mode_index(p0->levels == 0 ? GS_CONT
+                                    : (p0->levels == 2 || p0->levels == 4 || p0->levels == 8) ? p0->levels
+                                                                                                : GS_QATAN);
 
   chirp_of(0, ra.q1y, ra.q1x);
   ra.phase0 = phase;
@@ -1192,7 +1196,10 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
     chirp_of((j + 1) % P, ra.qoy, ra.qox);
     ra.phase_out = s == steps - 1 ? phase : nullptr;
     ra.levels_out = s == steps - 1 ? levels : nullptr;
-    hipLaunchKernelGGL(rk.gs_row_general, rows, dim3(rk.threads), rk.lds, stream, ra);
+    // steady-state variant unless the step needs illumination or produces outputs
+    void (*row)(GsRowArgs) =
+        (illumination || ra.phase_out || ra.levels_out) ? rk.gs_row_general : rk.gs_row_mp[mp_mode];
+    hipLaunchKernelGGL(row, rows, dim3(rk.threads), rk.lds, stream, ra);
   }
   if (nmse) {
     // the final state at every plane: its start pass for that plane's chirp, then an NMSE-only pass

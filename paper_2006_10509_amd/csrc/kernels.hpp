@@ -608,8 +608,11 @@ __device__ __forceinline__ float2 slm_constrain_rt(float2 g, const SlmConstraint
 // transform.  MODE >= 0 with FRES fixed is the steady-state kernel (no
 // illumination, no outputs); MODE < 0 takes the mode, the Fresnel flag, the
 // illumination and the output arrays at run time (the pass that produces the
-// returned state, and illuminated runs).
-template <int N, int MODE, bool FRES>
+// returned state, and illuminated runs).  MP (MODE >= 0): the steady-state
+// step of multi-plane GS, whose field leaves through the next plane's chirp
+// (qoy, qox; null for a Fourier plane) and arrives through this plane's (q1y,
+// q1x; null likewise), both tables loaded with the field.
+template <int N, int MODE, bool FRES, bool MP = false>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   a.select_item();
   using C = RowCfg<N>;
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
-  const bool fres = GENERAL ? (a.q1y != nullptr) : FRES;
+  const bool fres = (GENERAL || MP) ? (a.q1y != nullptr) : FRES;
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
   for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
   // general pass: the illumination and an outgoing chirp are loaded with the
@@ -643,13 +646,23 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   QO qo;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if (fres) qx.begin(a.q1x, t);
-  if constexpr (GENERAL) {
+  if constexpr (GENERAL || MP) {
     if (a.q_out_set && a.qoy) qo.begin(a.qox, t);
   }
   if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
-  if constexpr (!GENERAL) {
+  if constexpr (MP) {
+    const bool fres_out = a.qoy != nullptr;
+    const float2 qoy = fres_out ? a.qoy[rt.y] : make_float2(1.f, 0.f);
+    for_layout<LF>(t, [&](int s, int x) {
+      float2 g = v[s];
+      if (fres) g = cmulconj(g, cmul(qy, qx.at(s, x)));
+      int level;
+      const float2 u = slm_constrain<MODE>(g, a.slm, level);
+      v[s] = fres_out ? cmul(u, cmul(qoy, qo.at(s, x))) : u;
+    });
+  } else if constexpr (!GENERAL) {
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
       float2 q;
@@ -1206,6 +1219,7 @@ struct RowKernels {
   void (*gs_start)(GsRowArgs);
   void (*gs_row[5][2])(GsRowArgs);   // steady state [gs_mode_index][Fresnel]
   void (*gs_row_general)(GsRowArgs); // outputs / illumination / any mode
+  void (*gs_row_mp[5])(GsRowArgs);   // multi-plane steady state [gs_mode_index]
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
   void (*ospr_ca)(OsprRowArgs);   // pass C, then the next subframe's pass A
@@ -1265,6 +1279,11 @@ LengthEntry make_length_entry() {
   e.row.gs_row[4][0] = k_gs_row<N, GS_Q8, false>;
   e.row.gs_row[4][1] = k_gs_row<N, GS_Q8, true>;
   e.row.gs_row_general = k_gs_row<N, -1, false>;
+  e.row.gs_row_mp[0] = k_gs_row<N, GS_CONT, false, true>;
+  e.row.gs_row_mp[1] = k_gs_row<N, GS_QATAN, false, true>;
+  e.row.gs_row_mp[2] = k_gs_row<N, GS_Q2, false, true>;
+  e.row.gs_row_mp[3] = k_gs_row<N, GS_Q4, false, true>;
+  e.row.gs_row_mp[4] = k_gs_row<N, GS_Q8, false, true>;
   e.row.ospr_a = k_ospr_a<N>;
   e.row.ospr_c = k_ospr_c<N, false>;
   e.row.ospr_ca = k_ospr_c<N, true>;
