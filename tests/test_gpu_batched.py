@@ -100,3 +100,46 @@ def test_batched_argument_checks():
         hg.hg_gs_iterate_batched(plan, dev(targets), dev(phases), 2, ws)
     assert hg.workspace_bytes_batched(plan, 1) == plan.workspace_bytes()
     assert hg.workspace_bytes_batched(plan, 0) == 0
+
+
+def batched_level_states(plan, targets, phases, iters):
+    """Level maps of every state 0..iters of every item, one batched iteration
+    per call (bitwise the same as one long call), plus the NMSE of one long call."""
+    torch = torch_mod()
+    b = targets.shape[0]
+    t = dev(targets)
+    ws = torch.empty(hg.workspace_bytes_batched(plan, b), dtype=torch.uint8, device="cuda")
+    ph = dev(phases.copy())
+    lv = torch.zeros(targets.shape, dtype=torch.uint8, device="cuda")
+    hg.hg_gs_iterate_batched(plan, t, ph, 0, ws, levels=lv)
+    states = [host(lv).copy()]
+    for _ in range(iters):
+        hg.hg_gs_iterate_batched(plan, t, ph, 1, ws, levels=lv)
+        states.append(host(lv).copy())
+    full_ph, full_lv, nm = run_batched(plan, targets, phases, iters)
+    assert np.array_equal(full_lv, states[-1])
+    return [[s[i] for s in states] for i in range(b)], nm
+
+
+# (height, width, iterations) per shape class of the 64-hologram mix, Fourier, L = 4
+MIX_CLASSES = [(512, 512, 10), (1024, 1024, 6), (2048, 2048, 3), (1080, 1920, 4)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("h,w,iters", MIX_CLASSES)
+def test_mix_shape_class_item_against_oracle(h, w, iters):
+    """One item of each shape class of the mixed batch (its own seed from the
+    mix, run in a batch of two of that class as the mix runs it) against the
+    oracle: levels of every state outside the boundary band and the NMSE of
+    every state, the oracle restarted from the GPU's state at an in-band tie."""
+    from test_gpu_gs import check_quantised_segments
+    mix = [(hh, ww, seed) for hh, ww, seed in wl.batched_mix() if (hh, ww) == (h, w)]
+    seeds = [mix[0][2], mix[-1][2]]
+    print(f"mix class {h}x{w}: seeds {seeds}, {iters} iterations", flush=True)
+    ts, ps = zip(*[wl.target_and_phase(h, w, s) for s in seeds])
+    targets, phases = np.stack(ts), np.stack(ps)
+    plan = make_plan(h, w, 4, False)
+    states, nm = batched_level_states(plan, targets, phases, iters)
+    i = 1            # the class's last item: the second of its batch
+    restarts = check_quantised_segments(targets[i], phases[i], iters, 4, None, None, nm[i], states[i])
+    print(f"oracle restarted at states {restarts}")

@@ -66,12 +66,13 @@ def gpu_level_states(plan, target, phi0, iters, illum=None):
     return states
 
 
-def check_quantised_segments(target, phi0, iters, levels, fres, illum, nm, states):
-    """Levels and NMSE of every GPU state against the oracle, restarting the
-    oracle from the GPU's state at each in-band difference.  Returns the
-    states at which it was restarted."""
+def check_quantised_segments(target, phi0, iters, levels, fres, illum, nm, states, k0=0):
+    """Levels and NMSE of every GPU state k0..iters against the oracle,
+    restarting the oracle from the GPU's state at each in-band difference.
+    k0 > 0 starts from the GPU's state k0 (phi0 is then unused).  Returns the
+    states at which the oracle was restarted."""
     restarts = []
-    k0, start = 0, phi0
+    start = phi0 if k0 == 0 else states[k0].astype(np.float64) * (2 * np.pi / levels)
     while True:
         ref = oracle.gs_iterate(target, start, iters - k0, levels=levels, illumination=illum, fresnel=fres, trace=True)
         diverged = None
@@ -88,7 +89,9 @@ def check_quantised_segments(target, phi0, iters, levels, fres, illum, nm, state
                 break
         if diverged is None or diverged == iters:
             return restarts
-        assert not restarts or diverged > restarts[-1], "restarted oracle differs from its own start state"
+        # a run started from a GPU state reproduces that state exactly
+        assert diverged > k0 or (k0 == 0 and not restarts and start is phi0), \
+            "restarted oracle differs from its own start state"
         restarts.append(diverged)
         k0 = diverged
         start = states[diverged].astype(np.float64) * (2 * np.pi / levels)
@@ -125,9 +128,14 @@ def test_gs_fourier_256_continuous_20_iterations():
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gs_fresnel_1024_L8_100it.json")
 
 
+@pytest.mark.timeout(900)
 def test_gs_fresnel_1024_L8_full_100_iterations_against_stored_oracle():
     """The full 1024x1024 Fresnel 8-level workload in the launch shape bench.py
-    times, against the oracle results stored by tests/golden/make_golden.py."""
+    times, against the oracle results stored by tests/golden/make_golden.py:
+    every state's levels outside the boundary band and its NMSE, up to the
+    first in-band decision that went the other way; from there the oracle
+    runs live from the GPU's state (restarted again at each later tie) up to
+    state 100."""
     w = wl.GS_FRESNEL_1024
     print(f"gs {w.name} full", flush=True)
     with open(GOLDEN) as f:
@@ -136,8 +144,6 @@ def test_gs_fresnel_1024_L8_full_100_iterations_against_stored_oracle():
     plan = make_plan(w.height, w.width, w.levels, True)
     phase, lev, nm = run_gs(plan, t, phi, w.iterations)
     ref_nmse = np.array(gold["nmse"])
-    rel = np.abs(nm - ref_nmse) / ref_nmse
-    assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
     states = gpu_level_states(plan, t, phi, w.iterations)
     assert np.array_equal(states[-1], lev)
     first = None
@@ -151,7 +157,14 @@ def test_gs_fresnel_1024_L8_full_100_iterations_against_stored_oracle():
             assert hashlib.sha256(flat.tobytes()).hexdigest() == st["sha256"], f"state {k}: out-of-band difference"
             break
         assert hashlib.sha256(flat.tobytes()).hexdigest() == st["sha256"], f"state {k}: out-of-band difference"
-    print(f"first in-band divergence at state {first}")
+        assert abs(nm[k] - ref_nmse[k]) <= NMSE_TOL * ref_nmse[k], k
+    print(f"first in-band divergence at state {first}", flush=True)
+    if first is not None:
+        # from the tie on, the stored trajectory is no longer the GPU's: run the
+        # oracle live from the GPU's state there, segment by segment, to state 100
+        restarts = check_quantised_segments(t, None, w.iterations, w.levels, fresnel_dict(w), None, nm, states,
+                                            k0=first)
+        print(f"oracle restarted live at states {[first] + restarts}")
 
 
 def test_gs_fresnel_1024_L8_first_10_iterations():

@@ -4,6 +4,10 @@ Bars: binary levels identical except where |Re G| < 1e-5 |G| (the sign
 decision's boundary band, oracle G); time-averaged intensity relative L2
 <= 1e-5 plus the exact effect of the in-band flips; NMSE within 1e-4
 relative.  Properties at full size: sum I = N_px^2, centro-symmetry."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -72,6 +76,57 @@ def test_ospr_full_size_properties():
     assert np.array_equal(holo[0][~band], (g0.real < 0)[~band].astype(np.uint8))
 
 
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def check_against_stored_oracle(gold, holo, inten, nm, n_avg):
+    """Full-size comparison with oracle results stored by make_golden.py.
+
+    Levels: every subframe's map equals the oracle's outside the sign band
+    (masked SHA-256); in-band pixels may go either way and are counted.
+    Intensity: (a) exactly the average of |FFT2 h_n|^2 over the GPU's own
+    holograms (FP64 library FFT, relative L2 <= 1e-5), and (b) against the
+    oracle's stored block sums and sampled pixels within 1e-5 plus the bound
+    on the in-band flips' effect (each changes FFT2 h by 2 everywhere);
+    NMSE within 1e-4 relative plus the same bound."""
+    n_total, h, w = holo.shape
+    npx = h * w
+    flips = 0
+    for sub in gold["subframes"]:
+        n = sub["n"]
+        idx = np.array(sub["band_index"], dtype=np.int64)
+        flat = holo[n].ravel().copy()
+        flips += int((flat[idx] != np.array(sub["band_level"], dtype=np.uint8)).sum())
+        flat[idx] = 255
+        assert hashlib.sha256(flat.tobytes()).hexdigest() == sub["masked_sha256"], f"subframe {n}: out-of-band level"
+    # (a) the GPU's intensity is the average replay of the GPU's own holograms
+    acc = np.zeros((h, w))
+    for n in range(n_total):
+        hn = 1.0 - 2.0 * holo[n].astype(np.float64)
+        acc += np.abs(np.fft.fft2(hn)) ** 2
+    exact = np.fft.fftshift(acc / n_total)
+    assert rel_l2(inten, exact) <= 1e-5
+    # (b) against the stored oracle values
+    tol = 1e-5 + 4.0 * flips / (np.sqrt(npx) * n_avg)
+    blocks = inten.astype(np.float64).reshape(64, h // 64, 64, w // 64).sum(axis=(1, 3)).ravel()
+    assert rel_l2(blocks, np.array(gold["block_sums_64x64"])) <= tol
+    got = inten.ravel()[np.array(gold["sample_index"], dtype=np.int64)]
+    assert rel_l2(got, np.array(gold["sample_value"])) <= tol
+    assert abs(nm - gold["nmse"]) <= 1e-4 * gold["nmse"] + tol
+    print(f"{flips} in-band flips over {n_total} subframes; NMSE {nm:.6f} (oracle {gold['nmse']:.6f})")
+
+
+@pytest.mark.timeout(600)
+def test_ospr_2048_24_subframes_against_stored_oracle():
+    """The 2048x2048, 24-subframe workload in the launch shape bench.py times."""
+    w = wl.OSPR_2048
+    print(f"ospr {w.name} against stored oracle", flush=True)
+    with open(os.path.join(GOLDEN_DIR, "ospr_2048_24sub.json")) as f:
+        gold = json.load(f)
+    inten, holo, nm = run_ospr(w.target(), w.subframe_phases())
+    check_against_stored_oracle(gold, holo, inten, nm, w.subframes)
+
+
 def test_ospr_optional_outputs():
     h, w = 128, 256
     t = wl.target_amplitude(h, w, seed=1)
@@ -127,6 +182,16 @@ def test_ospr_pairs_equal_plain_gpu_ospr_on_quarter_turned_phases():
     qi, qh, _ = run_ospr(t, expanded)
     assert (ph != qh).mean() <= 1e-4
     assert rel_l2(pi, qi) <= 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_ospr_pairs_2048_12_pairs_against_stored_oracle():
+    w = wl.OSPR_2048
+    print(f"ospr pairs {w.name} against stored oracle", flush=True)
+    with open(os.path.join(GOLDEN_DIR, "ospr_pairs_2048_12pairs.json")) as f:
+        gold = json.load(f)
+    inten, holo, nm = run_pairs(w.target(), w.subframe_phases(12))
+    check_against_stored_oracle(gold, holo, inten, nm, w.subframes)
 
 
 def test_ospr_pairs_full_size_properties():

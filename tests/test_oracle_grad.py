@@ -115,3 +115,26 @@ def test_descent_reduces_loss_and_reports_every_state():
     assert out["loss"][0] == first
     last = oracle.loss_and_gradient(out["phase"], targets, planes, want_grad=False)[0]
     assert out["loss"][-1] == last
+
+
+def test_gradient_matches_central_differences_at_64x64_three_planes():
+    """The gradient workload's own geometry at 64x64: Fresnel planes at 0.40,
+    0.45 and 0.50 m (532 nm, 8 um), its seeded synthetic targets (200 + j) and
+    starting phase (300); FP64 central differences at every pixel."""
+    from paper_2006_10509_amd import workloads as wl
+    h = w = 64
+    planes = [dict(wavelength=532e-9, pitch=8e-6, distance=z) for z in (0.40, 0.45, 0.50)]
+    targets = [wl.target_amplitude(h, w, 200 + j).astype(np.float64) for j in range(3)]
+    phi = wl.uniform_phase(h, w, 300).astype(np.float64)
+    loss, g, _ = oracle.loss_and_gradient(phi, targets, planes)
+    step = 1e-5
+    fd = np.zeros_like(phi)
+    for k in range(phi.size):
+        e = np.zeros(phi.size)
+        e[k] = step
+        e = e.reshape(phi.shape)
+        lp = oracle.loss_and_gradient(phi + e, targets, planes, want_grad=False)[0]
+        lm = oracle.loss_and_gradient(phi - e, targets, planes, want_grad=False)[0]
+        fd.flat[k] = (lp - lm) / (2 * step)
+    assert np.abs(fd - g).max() <= 1e-6 * np.abs(g).max()
+    assert np.linalg.norm(fd - g) <= 1e-7 * np.linalg.norm(g)

@@ -230,3 +230,92 @@ def test_angular_spectrum_gs_consistent_target_is_a_fixed_point():
     out = oracle.gs_iterate(t, phi, 3, angular=ANGULAR)
     assert max(out["nmse"]) <= 1e-24
     assert np.abs(np.angle(np.exp(1j * (out["phase"] - phi)))).max() <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# non-uniform illumination A (the SLM amplitude the constraint keeps)
+# ---------------------------------------------------------------------------
+def test_worked_2x2_four_levels_with_illumination():
+    """Hand-worked L = 4 case with A = [[2, 1], [1, 1]]; dropping A from the
+    constraint or squaring it changes every value below."""
+    t_amp = np.array([[1.0, 0.0], [1.0, 2.0]])            # FFT order T_f = [[2, 1], [0, 1]]
+    phi0 = np.array([[0.0, np.pi / 2], [np.pi, 0.0]])     # H0 = A exp(i phi0) = [[2, i], [-1, 1]]
+    amp = np.array([[2.0, 1.0], [1.0, 1.0]])
+    out = oracle.gs_iterate(t_amp, phi0, 1, levels=4, illumination=amp)
+    # R0 = [[2+i, -i], [2+i, 4-i]], I0 = [[5, 1], [5, 17]] (sum 28 = 4 sum A^2);
+    # against T~ = [[4, 1], [0, 1]]/6: differences (-41, -11, 15, 37)/84
+    # -> 3396/7056 / (1/2) = 283/294
+    assert abs(out["nmse"][0] - 283.0 / 294.0) <= 1e-14
+    # G = IFFT2(T_f R0/|R0|) has angles -0.126, 1.205, 0.166, 0.539 rad
+    # -> levels [[0, 1], [0, 0]], H1 = [[2, i], [1, 1]]
+    assert out["levels"].tolist() == [[0, 1], [0, 0]]
+    # R1 = [[4+i, 2-i], [i, 2-i]], I1 = [[17, 5], [1, 5]]: differences (-5, 1, 3, 1)/84
+    # -> 36/7056 / (1/2) = 1/98
+    assert abs(out["nmse"][1] - 1.0 / 98.0) <= 1e-14
+
+
+def gaussian_illumination(h, w, waist=0.35):
+    y = (np.arange(h) - h / 2 + 0.5) / (waist * h)
+    x = (np.arange(w) - w / 2 + 0.5) / (waist * w)
+    return np.exp(-(y[:, None] ** 2 + x[None, :] ** 2))
+
+
+@pytest.mark.parametrize("levels", [0, 8])
+@pytest.mark.parametrize("fresnel", [None, FRESNEL])
+def test_consistent_target_with_illumination_is_fixed_point(levels, fresnel):
+    """T = |FFT2(Q1 A exp(i phi*))| with a Gaussian A: zero NMSE and phi* kept.
+    The loop without A, or with A squared, sees a different replay field."""
+    h, w = 32, 40
+    rng = np.random.default_rng(22)
+    amp = gaussian_illumination(h, w)
+    if levels:
+        phi_star = rng.integers(0, levels, (h, w)) * TWO_PI / levels
+    else:
+        phi_star = rng.uniform(0, TWO_PI, (h, w))
+    q1 = oracle.source_chirp(h, w, fresnel)
+    t_amp = np.fft.fftshift(np.abs(np.fft.fft2(q1 * amp * np.exp(1j * phi_star))))
+    out = oracle.gs_iterate(t_amp, phi_star, 3, levels=levels, fresnel=fresnel, illumination=amp)
+    assert max(out["nmse"]) <= 1e-24
+    assert np.abs(np.angle(np.exp(1j * (out["phase"] - phi_star)))).max() <= 1e-10
+    # the same target without the illumination is far from consistent
+    plain = oracle.gs_iterate(t_amp, phi_star, 0, levels=levels, fresnel=fresnel)
+    assert plain["nmse"][0] > 1e-3
+
+
+@pytest.mark.parametrize("levels", [0, 8, 2])
+@pytest.mark.parametrize("fresnel", [None, FRESNEL])
+def test_fienup_error_never_increases_with_illumination(levels, fresnel):
+    """Error reduction with A non-uniform: the SLM projection A P(G) is still
+    the nearest point of its set, so the Fienup error stays monotone."""
+    t, phi = synthetic(40, 48, 31 + levels)
+    amp = 0.2 + gaussian_illumination(40, 48)
+    out = oracle.gs_iterate(t, phi, 20, levels=levels, fresnel=fresnel, fienup=True, illumination=amp)
+    e = np.array(out["fienup"])
+    assert np.all(e[1:] <= e[:-1] * (1 + 1e-12)), e
+    assert e[-1] < e[0]
+
+
+def test_multiplane_with_illumination_consistent_targets_are_a_fixed_point():
+    h, w = 20, 24
+    rng = np.random.default_rng(23)
+    phi = rng.uniform(0, TWO_PI, (h, w))
+    amp = 0.3 + gaussian_illumination(h, w)
+    planes = [FRESNEL, dict(FRESNEL, distance=0.4), None]
+    targets = [np.fft.fftshift(np.abs(np.fft.fft2(oracle.source_chirp(h, w, p) * amp * np.exp(1j * phi))))
+               for p in planes]
+    out = oracle.gs_multiplane(targets, phi, 3, planes, illumination=amp)
+    assert max(out["nmse"]) <= 1e-24
+    assert np.abs(np.angle(np.exp(1j * (out["phase"] - phi)))).max() <= 1e-10
+    bare = oracle.gs_multiplane(targets, phi, 0, planes)
+    assert min(bare["nmse"]) > 1e-3
+
+
+@pytest.mark.parametrize("levels", [0, 4])
+def test_multiplane_with_illumination_and_one_plane_is_gs(levels):
+    """gs_iterate is pinned with A by the hand-worked case and the fixed point."""
+    t, phi = synthetic(24, 32, 24)
+    amp = 0.1 + gaussian_illumination(24, 32)
+    a = oracle.gs_multiplane([t], phi, 5, [FRESNEL], levels=levels, illumination=amp)
+    b = oracle.gs_iterate(t, phi, 5, levels=levels, fresnel=FRESNEL, illumination=amp)
+    assert a["nmse"] == b["nmse"]
+    assert np.array_equal(a["phase"], b["phase"])
