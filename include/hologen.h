@@ -100,9 +100,11 @@ int32_t hg_length_supported(int32_t n);
  *       Q2 = exp(i pi (x^2 + y^2)/(lambda z)) at x = (k - W/2) lambda z/(W p),
  *       c  = exp(i 2 pi z / lambda) / (i lambda z) * p^2;
  *     SLM field in natural order, replay field in centred order.
- *   HG_ANGULAR: angular-spectrum propagation on the SLM's own grid (the
- *     near-field model that complements Sec. 3's Fresnel and Fraunhofer
- *     transforms):
+ *   HG_ANGULAR: angular-spectrum propagation on the SLM's own grid, a
+ *     method variant added here (the transfer-function form of scalar
+ *     diffraction: Goodman, Introduction to Fourier Optics, the angular
+ *     spectrum of plane waves and its propagation); the
+ *     paper itself names only Fourier and Fresnel holograms:
  *       U_z = IFFT2(FFT2(U_0) T),  T = exp(i 2 pi z sqrt(1/lambda^2 - fx^2 - fy^2))
  *     at fx = kx / (W p) for FFT index kx (kx - W from kx >= (W + 1) / 2 on),
  *     fy likewise; the inverse uses conj(T).  Both planes in natural order.

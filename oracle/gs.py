@@ -1,9 +1,8 @@
 """Gerchberg-Saxton error-reduction iteration (FP64).
 
-Test infrastructure only.  The paper's HoloGenAlgGSCuda implements
-"Gerchberg-Saxton and other iterative Fourier transform approaches" in the
-RunIterations() function of an algorithm object that holds the target,
-illumination and starting images (Sec. 4, Algorithm Interface; Sec. 7.3).  The
+Test infrastructure only.  The paper's HoloGenAlgGSCuda (Sec. 7.3) runs the
+GS iteration in the RunIterations() function of an algorithm object that holds
+the target, illumination and starting images (Sec. 4, Algorithm Interface).  The
 update rule is the textbook one (Gerchberg & Saxton, Optik 35, 1972; Fienup,
 Appl. Opt. 21, 1982, error-reduction form):
 

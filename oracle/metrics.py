@@ -1,7 +1,7 @@
 """Energy-normalised mean squared error of a replay intensity (FP64).
 
-Test infrastructure only.  The paper's Normaliser provides "fast vector
-normalisation" (Sec. 7.3) and its process monitor reports algorithm progress
+Test infrastructure only.  The paper's Normaliser (Sec. 7.3) normalises
+vectors on the GPU and its process monitor reports algorithm progress
 (Sec. 7.1); the error measure itself is unstated.  Reading used here: both
 intensities are normalised to unit total energy over the full frame and
 
