@@ -141,6 +141,23 @@ hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illu
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
                         hipStream_t stream);
 
+/* hg_gs_iterate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, bitwise the same results, with the workspace taken
+ * from a static device array of HG_NOALLOC_WORKSPACE_MAX bytes that the
+ * library holds on every device it runs on until the process ends.  The
+ * caller passes inputs and outputs only; the call allocates nothing (its
+ * first call on a device looks up that device's array).  Every call on one
+ * device shares that array and overwrites it, so calls that overlap on one
+ * device (other streams, other host threads) race: serialise them.  The
+ * passes write every workspace byte they read, so nothing needs clearing
+ * between calls.  Errors: HG_ERR_UNSUPPORTED_SIZE when hg_workspace_bytes(plan)
+ * exceeds HG_NOALLOC_WORKSPACE_MAX (every frame up to 2048 x 2048 fits);
+ * other arguments and errors as hg_gs_iterate. */
+#define HG_NOALLOC_WORKSPACE_MAX (64u << 20)
+hg_status hg_gs_iterate_noalloc(hg_plan plan, const float* target_amp, const float* illumination, float* phase,
+                                uint8_t* levels, float* nmse, int32_t iterations, hipStream_t stream);
+
 /* Gerchberg-Saxton on a batch of same-shape holograms in one launch per pass:
  * exactly hg_gs_iterate applied to each item b < batch (bitwise the same
  * results), with every pass launched once over all items, so that many small

@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -684,6 +685,38 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   return launch_status("hg_gs_iterate launch");
 }
 
+// Workspace of hg_gs_iterate_noalloc: one static array per device, so that
+// the call needs no allocation.  In host code `scratch` names a host-side
+// stand-in, never the device array: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[HG_NOALLOC_WORKSPACE_MAX];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr and a status
+// on failure).
+hg_status device_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HG_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HG_ERR_DEVICE, "device index out of range");
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = err;
+    g_scratch_ptr[dev] = err == hipSuccess ? ptr : nullptr;
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+    return fail(HG_ERR_DEVICE, std::string("hipGetSymbolAddress of the static workspace: ") +
+                                   hipGetErrorString(g_scratch_err[dev]));
+  *out = g_scratch_ptr[dev];
+  return HG_OK;
+}
+
 hg_status gs_validate(hg_plan p, const float* target_amp, const float* phase, int32_t iterations, void* workspace) {
   if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
@@ -874,6 +907,22 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
   if (p->desc.propagation == HG_ANGULAR)
     return gs_run_angular(p, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
   return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
+}
+
+hg_status hg_gs_iterate_noalloc(hg_plan p, const float* target_amp, const float* illumination, float* phase,
+                                uint8_t* levels, float* nmse, int32_t iterations, hipStream_t stream) {
+  if (!p) return fail(HG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
+  if (iterations < 0) return fail(HG_ERR_INVALID_ARGUMENT, "iterations must be >= 0");
+  if (p->ws_bytes > (size_t)HG_NOALLOC_WORKSPACE_MAX)
+    return fail(HG_ERR_UNSUPPORTED_SIZE, "the plan needs " + std::to_string(p->ws_bytes) +
+                                             " bytes of workspace, above HG_NOALLOC_WORKSPACE_MAX (" +
+                                             std::to_string((size_t)HG_NOALLOC_WORKSPACE_MAX) + ")");
+  void* ws = nullptr;
+  const hg_status sst = device_scratch(&ws);
+  if (sst != HG_OK) return sst;
+  return hg_gs_iterate(p, target_amp, illumination, phase, levels, nmse, iterations, ws, stream);
 }
 
 size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch) {

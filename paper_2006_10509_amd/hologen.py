@@ -40,7 +40,7 @@ HG_KERNEL_PROP_ROW = 6
 HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
-            "hg_propagate", "hg_gs_iterate", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
+            "hg_propagate", "hg_gs_iterate", "hg_gs_iterate_noalloc", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
             "hg_multiplane_workspace_bytes", "hg_gs_multiplane",
             "hg_ospr", "hg_ospr_pairs", "hg_search_workspace_bytes", "hg_pixel_search",
             "hg_grad_workspace_bytes", "hg_grad",
@@ -91,6 +91,8 @@ def library() -> ctypes.CDLL:
     lib.hg_propagate.restype = i32
     lib.hg_gs_iterate.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.hg_gs_iterate.restype = i32
+    lib.hg_gs_iterate_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
+    lib.hg_gs_iterate_noalloc.restype = i32
     lib.hg_workspace_bytes_batched.argtypes = [vp, i32]
     lib.hg_workspace_bytes_batched.restype = sz
     lib.hg_gs_iterate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, vp, vp]
@@ -250,6 +252,26 @@ def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
         _ptr(levels, torch.uint8, shape, "levels", optional=True),
         _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
         int(iterations), _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
+
+
+# bytes of the static device workspace hg_gs_iterate_noalloc uses (hologen.h)
+HG_NOALLOC_WORKSPACE_MAX = 64 << 20
+
+
+def hg_gs_iterate_noalloc(plan: Plan, target_amp, phase, iterations: int,
+                          illumination=None, levels=None, nmse=None, stream=None) -> None:
+    """hg_gs_iterate with the library's static per-device workspace: no
+    allocation in the call.  Calls on one device share that workspace, so
+    overlapping calls race."""
+    import torch
+    shape = (plan.height, plan.width)
+    _check(library().hg_gs_iterate_noalloc(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape, "illumination", optional=True),
+        _ptr(phase, torch.float32, shape, "phase"),
+        _ptr(levels, torch.uint8, shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
+        int(iterations), _stream(stream)))
 
 
 def hg_ospr_pairs(plan: Plan, target_amp, sub_phase, intensity, workspace, holograms=None,

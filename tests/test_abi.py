@@ -77,6 +77,7 @@ def test_null_arguments_are_rejected_before_any_device_work():
     assert lib.hg_propagate(None, 1, 1, 1, None, None) == hg.HG_ERR_INVALID_ARGUMENT
     assert lib.hg_gs_iterate(None, 1, None, 1, None, None, 3, 1, None) == hg.HG_ERR_INVALID_ARGUMENT
     assert lib.hg_ospr(None, 1, 1, 1, None, 1, None, 1, None) == hg.HG_ERR_INVALID_ARGUMENT
+    assert lib.hg_gs_iterate_noalloc(None, 1, None, 1, None, None, 3, None) == hg.HG_ERR_INVALID_ARGUMENT
     assert lib.hg_workspace_bytes(None) == 0
     assert lib.hg_plan_destroy(None) == hg.HG_OK
 
