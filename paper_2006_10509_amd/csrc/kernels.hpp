@@ -646,7 +646,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   QO qo;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if (fres) qx.begin(a.q1x, t);
-  if constexpr (GENERAL || MP) {
+  if constexpr (MP) {
+    if (a.qoy) qo.begin(a.qox, t);
+  } else if constexpr (GENERAL) {
     if (a.q_out_set && a.qoy) qo.begin(a.qox, t);
   }
   if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();

@@ -343,3 +343,27 @@ def test_multiplane_three_planes_match_oracle():
     assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
     l2, frac = phase_parity(ph, ref["phase"])
     assert l2 <= 1e-4 and frac <= 1e-4, (l2, frac)
+
+
+@pytest.mark.parametrize("levels", [4, 3])
+def test_multiplane_mixed_fresnel_and_fourier_planes_quantised_match_oracle(levels):
+    """Fresnel, Fourier, Fresnel planes in one run, at L = 4 (sign/magnitude
+    quantiser) and L = 3 (atan2 quantiser): every step's NMSE and the final
+    level map against the oracle.  The steady-state multi-plane row pass
+    then runs every combination of incoming and outgoing chirp (Fresnel to
+    Fourier, Fourier to Fresnel, Fresnel to Fresnel)."""
+    h, w = 64, 64
+    specs = [dict(wavelength=532e-9, pitch=8e-6, distance=0.45), None,
+             dict(wavelength=532e-9, pitch=8e-6, distance=0.5)]
+    planes = [hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_PHASE_QUANTISED, levels) if sp is None else
+              hg.Plan(w, h, hg.HG_FRESNEL, sp["wavelength"], sp["pitch"], sp["distance"],
+                      hg.HG_PHASE_QUANTISED, levels) for sp in specs]
+    targets = np.stack([wl.target_amplitude(h, w, seed=70 + j) for j in range(3)])
+    phi = wl.uniform_phase(h, w, seed=73)
+    iters = 3
+    ph, lv, nm = run_multiplane(planes, targets, phi, iters)
+    ref = oracle.gs_multiplane(list(targets), phi, iters, specs, levels=levels)
+    assert np.array_equal(lv, ref["levels"])
+    rel = np.abs(nm - np.array(ref["nmse"])) / np.array(ref["nmse"])
+    assert rel.max() <= NMSE_TOL, (rel.max(), int(rel.argmax()))
+    assert np.abs(ph - lv * (2 * np.pi / levels)).max() <= 1e-5
