@@ -61,6 +61,27 @@ def measured_traffic(kernel: str):
     return entry.get("bytes_per_launch")
 
 
+def host_identity() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, the CPUs this process
+    may use, the CPU model and the NumPy version."""
+    import platform
+    import numpy as np
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "cpu_model": model, "numpy": np.__version__}
+
+
 def cpu_baseline(workload, target, phi0, sample_iters: int):
     import oracle
     try:
@@ -75,7 +96,10 @@ def cpu_baseline(workload, target, phi0, sample_iters: int):
     return {"value": sample_iters / dt, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{sample_iters} of the {workload.iterations} iterations of the same "
                       f"{workload.height}x{workload.width} workload and inputs, FP64, "
-                      f"including its one extra NMSE transform ({dt:.1f} s)"}
+                      f"including its one extra NMSE transform ({dt:.1f} s)",
+            "threads": "one Python process; its FFT's batched small-DFT products run on the BLAS "
+                       f"thread pool ({threads} threads), the rest of NumPy on one thread",
+            "host": host_identity()}
 
 
 def time_to_nmse(hg, wl, torch, stream) -> dict:
@@ -404,6 +428,11 @@ def main() -> int:
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-CGH measurements")
     ap.add_argument("--grad-problems", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--driver", choices=("graph", "eager"), default="graph",
+                    help="how the timed steps are issued: one captured HIP graph replayed per step "
+                         "(default), or the library call per step; both are measured and reported")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload and its kernel timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -417,6 +446,8 @@ def main() -> int:
     from paper_2006_10509_amd import hologen as hg
     from paper_2006_10509_amd import workloads as wl
 
+    if args.headline_only:
+        args.no_grad = args.no_batched = args.no_cpu_baseline = True
     mixed = None
     if not (args.no_batched or args.calibrate_copy):
         log("generating the mixed-batch inputs")
@@ -448,22 +479,57 @@ def main() -> int:
     def step():
         hg.hg_gs_iterate(plan, t, phase, w.iterations, ws, levels=levels, nmse=nmse, stream=stream)
 
-    log(f"warmup {args.warmup} steps of {w.name}")
-    for _ in range(args.warmup):
-        step()
+    # The step captured once into a HIP graph: replaying it enqueues the same
+    # launches with the same arguments.  One eager step and one replay from
+    # the same SLM state must give bitwise the same results.
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            hg.hg_gs_iterate(plan, t, phase, w.iterations, ws, levels=levels, nmse=nmse)
+    stream.wait_stream(side)
     torch.cuda.synchronize()
-    first_nmse = float(nmse[-1].item())
+    snap = phase.clone()
+    step()
+    torch.cuda.synchronize()
+    eager_out = (phase.clone(), levels.clone(), nmse.clone())
+    phase.copy_(snap)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_same = all(torch.equal(a_, b_) for a_, b_ in zip((phase, levels, nmse), eager_out))
+    if not graph_same:
+        log("graph replay differs from the eager call: timing the eager driver only")
+    phase.copy_(snap)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed_steps(run, label):
+        log(f"warmup {args.warmup} steps of {w.name} ({label})")
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        log(f"timed {args.steps} steps ({label}): {el / args.steps * 1e3:.3f} ms/step, "
+            f"{w.iterations * args.steps / el:.0f} iterations/s, final NMSE {float(nmse[-1].item()):.6f}")
+        return el
+
+    eager_el = timed_steps(step, "eager calls")
+    graph_el = timed_steps(graph.replay, "graph replay") if graph_same else None
+    use_graph = args.driver == "graph" and graph_same
+    elapsed = graph_el if use_graph else eager_el
     ms_per_step = elapsed / args.steps * 1e3
     value = w.iterations * args.steps / elapsed
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.0f} iterations/s, "
-        f"final NMSE {first_nmse:.6f}")
+    drivers = {"eager": {"ms_per_step": round(eager_el / args.steps * 1e3, 4),
+                         "iterations_per_s": round(w.iterations * args.steps / eager_el, 1)},
+               "graph": None if graph_el is None else
+               {"ms_per_step": round(graph_el / args.steps * 1e3, 4),
+                "iterations_per_s": round(w.iterations * args.steps / graph_el, 1),
+                "bitwise_equal_to_eager": graph_same}}
 
     # per-kernel durations with HIP events on the launch stream, after the
     # timed region: every launch of the kernel runs TIMING_REPEATS times back
@@ -505,12 +571,14 @@ def main() -> int:
         b1024 = batched_1024(hg, wl, torch, stream)
         log(f"batched 1024^2: {b1024}")
 
-    srch = pixel_search_1024(hg, wl, torch, stream)
-    log(f"pixel search: {srch}")
-    osp = ospr_2048(hg, wl, torch, stream)
-    log(f"OSPR 2048: {osp}")
-    rf = rocfft_reference(torch, stream)
-    log(f"rocFFT reference: {rf}")
+    srch = osp = rf = None
+    if not args.headline_only:
+        srch = pixel_search_1024(hg, wl, torch, stream)
+        log(f"pixel search: {srch}")
+        osp = ospr_2048(hg, wl, torch, stream)
+        log(f"OSPR 2048: {osp}")
+        rf = rocfft_reference(torch, stream)
+        log(f"rocFFT reference: {rf}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -524,7 +592,9 @@ def main() -> int:
            "config": {"workload": w.name, "height": w.height, "width": w.width,
                       "iterations_per_step": w.iterations, "levels": w.levels, "propagation": "fresnel",
                       "wavelength_m": w.wavelength, "pitch_m": w.pitch, "distance_m": w.distance,
-                      "target_seed": w.target_seed, "phase_seed": w.phase_seed},
+                      "target_seed": w.target_seed, "phase_seed": w.phase_seed,
+                      "driver": "hip_graph_replay" if use_graph else "eager_calls"},
+           "drivers": drivers,
            "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
            "batched_mix": mix, "batched_1024": b1024, "ospr": osp, "pixel_search": srch,
            "rocfft_reference": rf}
