@@ -30,6 +30,8 @@ step by step in the order the method performs it:
                   loss, its Wirtinger gradient and Adam (Kingma & Ba 2015).
   search.py       single-pixel direct binary search and simulated annealing
                   (the paper's HoloGenAlgDSCuda / HoloGenAlgSACuda, Sec. 7.3).
+  window.py       GS with a signal window (region of interest) in the replay
+                  plane (Fienup 1982; Wyrowski & Bryngdahl 1988).
 
 Where the paper is silent, each module's docstring states the reading it
 takes.  Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
@@ -45,6 +47,7 @@ from .gs import gs_iterate, gs_multiplane
 from .ospr import ospr, ospr_pairs
 from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
 from .search import pixel_search
+from .window import gs_window, window_nmse
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
@@ -53,4 +56,5 @@ __all__ = [
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
     "binarise", "nmse", "gs_iterate", "gs_multiplane", "ospr", "ospr_pairs",
     "source_chirp", "loss_and_gradient", "adam_update", "grad_descent", "pixel_search",
+    "gs_window", "window_nmse",
 ]
