@@ -157,15 +157,18 @@ def time_to_nmse(hg, wl, torch, stream) -> dict:
 
 
 def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
-    """The 3-plane gradient workload: `problems` problems of 500 Adam steps each
-    (one hg_grad_adam call per problem), problem-steps/s."""
+    """The 3-plane gradient workload: `problems` problems of 500 Adam steps
+    each, all in one hg_grad_adam_batched call (problems on grid.y), against
+    one hg_grad_adam call per problem; problem-steps/s, results compared
+    bitwise."""
     w = wl.GRAD_3PLANE_1024
     planes = [hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, z, hg.HG_PHASE, 0)
               for z in w.distances]
     gws = hg.grad_workspace(planes)
     data = [(torch.from_numpy(w.targets(bi)).cuda(), torch.from_numpy(w.phase0(bi)).cuda())
             for bi in range(problems)]
-    losses = torch.empty((problems, w.steps + 1), dtype=torch.float32, device="cuda")
+    seq_losses = torch.empty((problems, w.steps + 1), dtype=torch.float32, device="cuda")
+    seq_phase = []
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record(stream)
@@ -173,10 +176,30 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
         ph = p0.clone()
         m = torch.zeros_like(ph)
         v = torch.zeros_like(ph)
-        hg.hg_grad_adam(planes, tg, ph, m, v, w.steps, gws, lr=w.lr, loss=losses[bi], stream=stream)
+        hg.hg_grad_adam(planes, tg, ph, m, v, w.steps, gws, lr=w.lr, loss=seq_losses[bi], stream=stream)
+        seq_phase.append(ph)
     b.record(stream)
     b.synchronize()
-    ms = a.elapsed_time(b)
+    seq_ms = a.elapsed_time(b)
+    tb = torch.stack([tg for tg, _ in data])
+    pb0 = torch.stack([p0 for _, p0 in data])
+    bws = hg.grad_workspace_batched(planes, problems)
+    losses = torch.empty((problems, w.steps + 1), dtype=torch.float32, device="cuda")
+
+    def run_batched():
+        ph = pb0.clone()
+        m = torch.zeros_like(ph)
+        v = torch.zeros_like(ph)
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_grad_adam_batched(planes, tb, ph, m, v, w.steps, bws, lr=w.lr, loss=losses, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b), ph
+
+    run_batched()
+    ms, bph = run_batched()
+    same = bool(torch.equal(losses, seq_losses) and all(torch.equal(bph[i], seq_phase[i]) for i in range(problems)))
     fin = losses[:, -1].cpu().numpy()
     # the same problems with plane-by-plane multi-plane GS (continuous phase),
     # 100 iterations of 3 steps each: summed final NMSE over the planes
@@ -194,8 +217,12 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
     return {"workload": w.name, "problems": problems, "steps": w.steps, "planes": len(w.distances),
             "multiplane_gs": {"iterations": iters, "ms": round(mp_ms, 2),
                               "final_loss_mean": float(mp_final.mean())},
+            "launch": "one hg_grad_adam_batched call for all problems",
             "ms": round(ms, 2), "problem_steps_per_s": round(problems * w.steps / (ms * 1e-3), 1),
             "ms_per_step": round(ms / (problems * w.steps), 4),
+            "sequential_ms": round(seq_ms, 2),
+            "sequential_problem_steps_per_s": round(problems * w.steps / (seq_ms * 1e-3), 1),
+            "batched_equals_sequential_bitwise": same,
             "final_loss_mean": float(fin.mean()), "initial_loss_mean": float(losses[:, 0].mean().item())}
 
 
@@ -324,6 +351,29 @@ def batched_mix(hg, wl, torch, stream, inputs, iterations: int = 50) -> dict:
     graph_ms = min(run_graph() for _ in range(3))
     same = all(torch.equal(bp[sh][k], seq_phase[i]) and torch.equal(bn[sh][k], seq_nmse[i])
                for sh in shapes for k, i in enumerate(groups[sh]))
+
+    # the four batched calls on four streams of default priority, so that the
+    # shapes' passes can run side by side on the GPU
+    side_streams = [torch.cuda.Stream() for _ in shapes]
+
+    def run_streams():
+        for sh in shapes:
+            bp[sh].copy_(bp0[sh])
+        torch.cuda.synchronize()
+        a.record(stream)
+        for sh, ss in zip(shapes, side_streams):
+            ss.wait_stream(stream)
+            hg.hg_gs_iterate_batched(plans[sh], bt[sh], bp[sh], iterations, bws[sh], nmse=bn[sh], stream=ss)
+        for ss in side_streams:
+            stream.wait_stream(ss)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    run_streams()
+    streams_ms = min(run_streams() for _ in range(3))
+    same = same and all(torch.equal(bp[sh][k], seq_phase[i]) and torch.equal(bn[sh][k], seq_nmse[i])
+                        for sh in shapes for k, i in enumerate(groups[sh]))
     n = len(items)
     return {"workload": "gs_fourier_L4_50it_mixed64", "holograms": n, "iterations": iterations,
             "sequential_ms": round(seq_ms, 2), "batched_ms": round(bat_ms, 2),
@@ -331,6 +381,8 @@ def batched_mix(hg, wl, torch, stream, inputs, iterations: int = 50) -> dict:
             "batched_holograms_per_s": round(n / (bat_ms * 1e-3), 1),
             "speedup": round(seq_ms / bat_ms, 3), "identical_results": bool(same),
             "graph_ms": round(graph_ms, 2), "graph_holograms_per_s": round(n / (graph_ms * 1e-3), 1),
+            "four_streams_ms": round(streams_ms, 2),
+            "four_streams_holograms_per_s": round(n / (streams_ms * 1e-3), 1),
             "launches": f"{len(shapes)} batched calls vs {n} single calls"}
 
 
@@ -401,6 +453,51 @@ def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
             "trial_pass_gbs": round(trial_bytes / (ms * 1e-3 / n_trials) / 1e9, 1)}
 
 
+SWEEP_SIZES = (256, 512, 1024, 2048, 4096, 8192)
+
+
+def size_sweep(hg, wl, torch, stream, sizes=SWEEP_SIZES, iterations: int = 20) -> list:
+    """The headline's GS (Fresnel, 532 nm, 8 um, 0.5 m, 8 levels, NMSE of every
+    state) on square frames from 256^2 to 8192^2, whose working set (field,
+    target, phase: 20 B/px) passes the 256 MiB last-level cache above 4096^2.
+    The target is the 1024^2 workload's target repeated periodically (cropped
+    below 1024), the starting phase uniform from seed 3.  us per iteration,
+    algorithmic GB/s at 36 B/px and its fraction of 8 TB/s."""
+    w = wl.GS_FRESNEL_1024
+    base_t, _ = w.inputs()
+    base = torch.from_numpy(base_t).cuda()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for n in sizes:
+        reps = (n + 1023) // 1024
+        t = base.repeat(reps, reps)[:n, :n].contiguous()
+        g = torch.Generator(device="cuda").manual_seed(3)
+        ph0 = torch.rand((n, n), generator=g, device="cuda", dtype=torch.float32) * (2 * 3.141592653589793)
+        plan = hg.Plan(n, n, hg.HG_FRESNEL, w.wavelength, w.pitch, w.distance, hg.HG_PHASE_QUANTISED, w.levels)
+        ws = plan.workspace()
+        nm = torch.empty(iterations + 1, dtype=torch.float32, device="cuda")
+        ph = ph0.clone()
+        hg.hg_gs_iterate(plan, t, ph, iterations, ws, nmse=nm, stream=stream)
+        times = []
+        for _ in range(3):
+            ph.copy_(ph0)
+            torch.cuda.synchronize()
+            a.record(stream)
+            hg.hg_gs_iterate(plan, t, ph, iterations, ws, nmse=nm, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        us = min(times) * 1e3 / iterations
+        gbs = sum(BYTES_PER_PX.values()) * n * n / (us * 1e-6) / 1e9
+        out.append({"n": n, "us_per_iteration": round(us, 2), "iterations_per_s": round(1e6 / us, 1),
+                    "algorithmic_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "working_set_mib": round(20 * n * n / 2 ** 20, 1), "final_nmse": float(nm[-1].item())})
+        log(f"  sweep {n}^2: {out[-1]}")
+        del ws, t, ph, ph0, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def rocfft_reference(torch, stream, n: int = 1024, reps: int = 200) -> dict:
     """torch.fft (rocFFT) forward + inverse 2D transform of one n x n complex64
     field, back to back: a vendor-library reference point, not part of the path."""
@@ -433,6 +530,9 @@ def main() -> int:
                          "(default), or the library call per step; both are measured and reported")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload and its kernel timings (for profiler runs)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 256^2 to 8192^2 size sweep")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the size sweep (for profiler runs), printed as one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -446,7 +546,7 @@ def main() -> int:
     from paper_2006_10509_amd import hologen as hg
     from paper_2006_10509_amd import workloads as wl
 
-    if args.headline_only:
+    if args.headline_only or args.sweep_only:
         args.no_grad = args.no_batched = args.no_cpu_baseline = True
     mixed = None
     if not (args.no_batched or args.calibrate_copy):
@@ -464,6 +564,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": src.numel() * 8,
                           "bytes_written_per_dispatch": dst.numel() * 8, "dispatches": 20}))
+        return 0
+    if args.sweep_only:
+        print(json.dumps({"size_sweep": size_sweep(hg, wl, torch, torch.cuda.current_stream())}), flush=True)
         return 0
     w = wl.GS_FRESNEL_1024
     target, phi0 = w.inputs()
@@ -580,6 +683,11 @@ def main() -> int:
         rf = rocfft_reference(torch, stream)
         log(f"rocFFT reference: {rf}")
 
+    sweep = None
+    if not (args.headline_only or args.no_sweep):
+        log("size sweep 256^2 .. 8192^2")
+        sweep = size_sweep(hg, wl, torch, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_sample_iters} iterations")
@@ -597,7 +705,7 @@ def main() -> int:
            "drivers": drivers,
            "roofline": roofline, "cpu_baseline": cpu, "time_to_nmse": ttn, "grad_cgh": gb,
            "batched_mix": mix, "batched_1024": b1024, "ospr": osp, "pixel_search": srch,
-           "rocfft_reference": rf}
+           "rocfft_reference": rf, "size_sweep": sweep}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -61,7 +61,11 @@ enum { HG_FORWARD = 1 /* SLM -> replay */, HG_INVERSE = -1 /* replay -> SLM */ }
 
 typedef struct {
   int32_t width, height;   /* SLM resolution in pixels; each must be a compiled
-                              transform length (hg_length_supported)            */
+                              transform length (hg_length_supported): 16, 24,
+                              32, 60, 64, 90, 120, 128, 256, 512, 1024, 1080,
+                              1280, 1536, 1920, 2048, 2160, 3840, 4096, 8192;
+                              any other value returns HG_ERR_UNSUPPORTED_SIZE
+                              (HG_ERR_INVALID_ARGUMENT outside [2, 8192])      */
   int32_t propagation;     /* HG_FOURIER, HG_FRESNEL or HG_ANGULAR               */
   double wavelength;       /* metres; Fresnel, angular: finite and > 0           */
   double pixel_pitch;      /* metres; Fresnel, angular: finite and > 0; angular
@@ -140,6 +144,28 @@ hg_status hg_propagate(hg_plan plan, const void* in_c64, void* out_c64, int32_t 
 hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illumination, float* phase,
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
                         hipStream_t stream);
+
+/* Gerchberg-Saxton with a signal window in the replay plane: the target is
+ * imposed only inside the window, the rest of the replay plane keeps the light
+ * the hologram sends there, and the error is measured inside the window.  The
+ * paper's application lets a user draw masks over its images (Sec. 7.1,
+ * HoloGenUIMask; Sec. 7.2, HoloGenMaskOptions) without saying how a mask
+ * enters the iteration; this is the signal-window form of error reduction
+ * (Fienup 1982; Wyrowski & Bryngdahl 1988):
+ *   M = ifftshift(window) != 0;  c = sqrt(H W sum A^2 / sum_M T_f^2)
+ *   R_k = FFT2(Q1 H_k);  nmse[k] = NMSE over M of (|R_k|^2, T_f^2)
+ *   R'_k = c T_f R_k / |R_k| on M,  R_k off M;  H_{k+1} = A P(conj(Q1) IFFT2(R'_k))
+ * with NMSE over M = sum_M (I/sum_M I - T/sum_M T)^2 / sum_M (T/sum_M T)^2
+ * (1 when no light reaches the window).  c puts the window's target at the
+ * field's energy, so each step is a nearest-point projection; a window
+ * covering the frame gives the iterates of hg_gs_iterate (up to rounding).
+ * window [H][W] uint8, centred like target_amp, nonzero inside (required);
+ * the target must not vanish on the whole window (else the error and c are
+ * not finite).  HG_FOURIER and HG_FRESNEL plans; other arguments, outputs and
+ * the workspace (hg_workspace_bytes) as hg_gs_iterate. */
+hg_status hg_gs_iterate_window(hg_plan plan, const float* target_amp, const uint8_t* window, const float* illumination,
+                               float* phase, uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                               hipStream_t stream);
 
 /* hg_gs_iterate for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -269,6 +295,24 @@ hg_status hg_grad(const hg_plan* planes, int32_t n_planes, const float* target_a
 hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* target_amp, float* phase,
                        float* adam_m, float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1,
                        float beta2, float eps, float* loss, void* workspace, hipStream_t stream);
+
+/* The gradient method on `batch` same-shape problems side by side: every
+ * pass is one launch over all problems (grid.y = problem), and each
+ * problem's results are bitwise those of the single-problem call.  Problem b
+ * uses target_amp + b n_planes H W (its n_planes targets), phase, grad,
+ * adam_m and adam_v + b H W, and loss + b (hg_grad_batched: one value) or
+ * loss + b (steps + 1) (hg_grad_adam_batched); the planes are shared.
+ * 1 <= batch <= 65535 and batch H W' < 2^32 (W' = W rounded up to the field's
+ * column-tile width).  workspace: hg_grad_workspace_bytes_batched(planes[0],
+ * n_planes, batch) bytes (the fields and accumulators of all problems are
+ * resident together).  Other arguments and errors as hg_grad / hg_grad_adam. */
+size_t hg_grad_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch);
+hg_status hg_grad_batched(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                          const float* phase, float* grad, float* loss, void* workspace, hipStream_t stream);
+hg_status hg_grad_adam_batched(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                               float* phase, float* adam_m, float* adam_v, int32_t steps, int32_t first_step,
+                               float lr, float beta1, float beta2, float eps, float* loss, void* workspace,
+                               hipStream_t stream);
 
 /* Diagnostics: per-kernel timing with HIP events.
  * hg_timing_begin makes every later launch of `kernel` made by calls on this

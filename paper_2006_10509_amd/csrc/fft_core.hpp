@@ -472,13 +472,19 @@ __device__ __forceinline__ void lds_fill(float2* dst, const float2* __restrict__
   }
 }
 
+// Twiddle images above this many complex words are not copied into LDS: the
+// transform reads them from the global image (a few hundred KiB at most,
+// resident in L2) where it uses them, leaving the LDS to the data.
+constexpr int TW_LDS_MAX_WORDS = 8704;
+
 // Twiddles of one pass kernel for the transform orders it runs (USE_F: the
 // forward radix order, USE_R: the reversed one).  When every set it needs
 // holds at most TW_REG_MAX values per thread, each thread loads its own
 // entries from the global twiddle image straight into registers: coalesced
 // loads that go out with the kernel's data loads and need neither LDS nor a
 // barrier.  Larger sets are copied into the workgroup's LDS at `lds_img`
-// (visible after the caller's barrier) and read from there.
+// (visible after the caller's barrier) and read from there, unless they
+// exceed TW_LDS_MAX_WORDS: those are read from the global image itself.
 template <class P, int THREADS, bool USE_F, bool USE_R>
 struct PassTwiddles {
   static constexpr bool PAL = P::PALINDROME;
@@ -488,10 +494,17 @@ struct PassTwiddles {
   static constexpr int LEN_R = TwRegs<P, true>::TOTAL * P::T;
   static constexpr bool IN_REGS = (!NEED_F || TwRegs<P, false>::TOTAL <= TW_REG_MAX) &&
                                   (!NEED_R || TwRegs<P, true>::TOTAL <= TW_REG_MAX);
+  static constexpr int IMAGE_WORDS = (NEED_F ? LEN_F : 0) + (NEED_R ? LEN_R : 0);
+  // Both orders' images: the LDS a launch of this length reserves is sized by
+  // the kernels that run both orders, so a kernel running one order must take
+  // the global path whenever those do.
+  static constexpr int FULL_WORDS = LEN_F + (PAL ? 0 : LEN_R);
+  // read at the point of use from the global image
+  static constexpr bool IN_GLOBAL = !IN_REGS && FULL_WORDS > TW_LDS_MAX_WORDS;
   // true when begin() writes LDS and the caller must barrier before run()
-  static constexpr bool USES_LDS = !IN_REGS;
-  // LDS words the twiddles take (0 in register mode)
-  static constexpr int LDS_WORDS = IN_REGS ? 0 : (NEED_F ? LEN_F : 0) + (NEED_R ? LEN_R : 0);
+  static constexpr bool USES_LDS = !IN_REGS && !IN_GLOBAL;
+  // LDS words the twiddles take (0 in register and global modes)
+  static constexpr int LDS_WORDS = USES_LDS ? IMAGE_WORDS : 0;
 
   TwRegs<P, false> f;
   TwRegs<P, true> r;
@@ -502,6 +515,9 @@ struct PassTwiddles {
     if constexpr (IN_REGS) {
       if constexpr (NEED_F) f.load(tw, t);
       if constexpr (NEED_R) r.load(twr, t);
+    } else if constexpr (IN_GLOBAL) {
+      img_f = tw;
+      img_r = twr;
     } else {
       float2* rimg = lds_img + (NEED_F ? LEN_F : 0);
       if constexpr (NEED_F) lds_fill<THREADS, LEN_F>(lds_img, tw);

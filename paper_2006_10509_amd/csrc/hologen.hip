@@ -314,7 +314,7 @@ hg_status launch_status(const char* what) {
 // Scalars [batch] | stats | NMSE partials [batch][kNmseChunk][workgroups] |
 // tiled targets [batch][tiles][H][C].  batch = 1 is the single-call layout.
 struct WsLayout {
-  size_t sc, stats, partials, target, total;
+  size_t sc, stats, partials, target, wpartials, total;
   size_t partial_stride, target_stride;   // floats per batch item
 };
 
@@ -333,7 +333,9 @@ WsLayout ws_layout(hg_plan p, int batch) {
   L.stats = L.sc + align_up((size_t)batch * sizeof(Scalars));
   L.partials = L.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   L.target = L.partials + align_up((size_t)batch * L.partial_stride * sizeof(float));
-  L.total = L.target + align_up((size_t)batch * L.target_stride * sizeof(float));
+  L.wpartials = L.target + align_up((size_t)batch * L.target_stride * sizeof(float));
+  // signal window (one hologram): three FP64 sums per column workgroup and state
+  L.total = L.wpartials + align_up((size_t)kNmseChunk * 3 * p->col_blocks * sizeof(double));
   return L;
 }
 
@@ -342,7 +344,8 @@ struct Workspace {
   Scalars* sc;
   double* stats;
   float* partials;
-  float* target;   // target amplitude tiled for the column pass (k_tile_target)
+  float* target;      // target amplitude tiled for the column pass (k_tile_target)
+  double* wpartials;  // signal-window error sums
 };
 
 Workspace carve(hg_plan p, void* ws, int batch = 1) {
@@ -350,7 +353,7 @@ Workspace carve(hg_plan p, void* ws, int batch = 1) {
   char* b = static_cast<char*>(ws);
   return {reinterpret_cast<float2*>(b), reinterpret_cast<Scalars*>(b + L.sc),
           reinterpret_cast<double*>(b + L.stats), reinterpret_cast<float*>(b + L.partials),
-          reinterpret_cast<float*>(b + L.target)};
+          reinterpret_cast<float*>(b + L.target), reinterpret_cast<double*>(b + L.wpartials)};
 }
 
 size_t npix(hg_plan p) { return (size_t)p->desc.width * (size_t)p->desc.height; }
@@ -363,34 +366,38 @@ int stats_blocks(size_t n) {
 }
 
 void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const float* illum, double intensity_sum,
-                   Scalars* out, hipStream_t s) {
+                   Scalars* out, hipStream_t s, const uint8_t* window = nullptr) {
   const size_t n = npix(p);
   const int nb = stats_blocks(n);
   // sum I of a GS state: N_px sum A^2 after the unnormalised FFT2; the
   // angular-spectrum replay pass sees H W times the unitary field, N_px^2 sum A^2
   const double a2_scale = p->desc.propagation == HG_ANGULAR ? (double)n * (double)n : (double)n;
-  hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats);
+  hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats, window);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, (const double*)w.stats, nb, n, illum ? 1 : 0,
                      intensity_sum, a2_scale, out);
 }
 
-// Workspace of the gradient method for `planes` replay planes:
-// field | dL/dphi accumulator | Scalars per plane | stats | loss partials
-// [kNmseChunk states][planes][column workgroups] | tiled target per plane.
+// Workspace of the gradient method for `batch` problems of `planes` replay
+// planes each: fields [batch] | dL/dphi accumulators [batch][H][W] | Scalars
+// [batch][planes] | stats | loss partials [batch][kNmseChunk states][planes]
+// [column workgroups] | tiled targets [batch][planes].  batch = 1 is the
+// single-problem layout.
 struct GradLayout {
   size_t acc, sc, stats, partials, target, target_stride, total;
+  size_t partial_stride;   // floats of loss partials per problem
 };
 
-GradLayout grad_layout(hg_plan p, int planes) {
+GradLayout grad_layout(hg_plan p, int planes, int batch = 1) {
   const size_t n = npix(p);
   GradLayout g{};
-  g.acc = align_up(field_elems(p) * sizeof(float2));
-  g.sc = g.acc + align_up(n * sizeof(float));
-  g.stats = g.sc + align_up((size_t)planes * sizeof(Scalars));
+  g.partial_stride = (size_t)kNmseChunk * planes * p->col_blocks;
+  g.acc = align_up((size_t)batch * field_elems(p) * sizeof(float2));
+  g.sc = g.acc + align_up((size_t)batch * n * sizeof(float));
+  g.stats = g.sc + align_up((size_t)batch * planes * sizeof(Scalars));
   g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
-  g.target = g.partials + align_up((size_t)kNmseChunk * planes * p->col_blocks * sizeof(float));
+  g.target = g.partials + align_up((size_t)batch * g.partial_stride * sizeof(float));
   g.target_stride = align_up((size_t)p->col_blocks * p->col->col.cols * p->desc.height * sizeof(float));
-  g.total = g.target + (size_t)planes * g.target_stride;
+  g.total = g.target + (size_t)batch * planes * g.target_stride;
   return g;
 }
 
@@ -412,13 +419,16 @@ hg_status validate_planes(const hg_plan* planes, int n_planes) {
 // One gradient evaluation per step for `steps` steps (Adam when m != null),
 // then, when final_loss, the loss of the state the last step leaves.
 // loss[k] receives the summed NMSE of state k (nullable).
-hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float* phase, float* grad, float* m,
-                   float* v, int steps, int first_step, float lr, float beta1, float beta2, float eps, float* loss,
-                   bool final_loss, void* workspace, hipStream_t stream) {
+// `batch` problems side by side (grid.y = problem): problem b uses
+// target_amp + b P H W, phase / grad / m / v + b H W and loss + b loss_stride,
+// and its arithmetic is exactly that of a single-problem call.
+hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_amp, float* phase, float* grad,
+                   float* m, float* v, int steps, int first_step, float lr, float beta1, float beta2, float eps,
+                   float* loss, size_t loss_stride, bool final_loss, void* workspace, hipStream_t stream) {
   hg_plan p0 = planes[0];
   const int W = p0->desc.width, H = p0->desc.height;
   const size_t n = npix(p0);
-  const GradLayout L = grad_layout(p0, P);
+  const GradLayout L = grad_layout(p0, P, batch);
   char* ws = static_cast<char*>(workspace);
   float2* field = reinterpret_cast<float2*>(ws);
   float* acc = reinterpret_cast<float*>(ws + L.acc);
@@ -430,16 +440,18 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
   const int cols = ck.cols;
   const uint32_t tiled_n = (uint32_t)p0->col_blocks * cols * H;
   const int nb = stats_blocks(n);
-  for (int j = 0; j < P; ++j) {
-    const float* tj = target_amp + (size_t)j * n;
-    float* tiled = reinterpret_cast<float*>(ws + L.target + (size_t)j * L.target_stride);
-    hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cols,
-                       tiled_n);
-    hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, (const float*)nullptr, n,
-                       stats);
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
-                       (double)n * (double)n, (double)n, sc + j);
-  }
+  for (int b = 0; b < batch; ++b)
+    for (int j = 0; j < P; ++j) {
+      const float* tj = target_amp + ((size_t)b * P + j) * n;
+      float* tiled = reinterpret_cast<float*>(ws + L.target + ((size_t)b * P + j) * L.target_stride);
+      hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cols,
+                         tiled_n);
+      hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, (const float*)nullptr, n,
+                         stats);
+      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
+                         (double)n * (double)n, (double)n, sc + (size_t)b * P + j);
+    }
+  const dim3 rows(p0->row_blocks, batch), tiles(p0->col_blocks, batch);
   GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
   fa.ft = p0->ft;
   fa.field = field;
@@ -447,6 +459,8 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
   fa.H = H;
   fa.tw = p0->tw_row[0];
   fa.twr = p0->tw_row[1];
+  fa.px = (uint32_t)n;
+  fa.fpx = (uint32_t)field_elems(p0);
   GsColArgs ca{};
   ca.ft = p0->ft;
   ca.field = field;
@@ -454,7 +468,13 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
   ca.H = H;
   ca.tw = p0->tw_col[0];
   ca.twr = p0->tw_col[1];
+  ca.px = (uint32_t)field_elems(p0);
+  ca.target_stride = (uint32_t)((size_t)P * L.target_stride / sizeof(float));
+  ca.sc_stride = (uint32_t)P;
+  ca.partial_stride = (uint32_t)L.partial_stride;
   GradRowArgs ga{};
+  ga.px = (uint32_t)n;
+  ga.fpx = (uint32_t)field_elems(p0);
   ga.ft = p0->ft;
   ga.field = field;
   ga.phase = phase;
@@ -490,14 +510,14 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
     for (int j = 0; j < P; ++j) {
       if (!started) {
         plane_chirp(j, fa.q1y, fa.q1x);
-        hipLaunchKernelGGL(rk.gs_start, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, fa);
+        hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, fa);
       }
       started = false;
       ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
       ca.sc = sc + j;
       ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * p0->col_blocks : nullptr;
       if (is_step && backward) {
-        hipLaunchKernelGGL(ck.grad_col, dim3(p0->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+        hipLaunchKernelGGL(ck.grad_col, tiles, dim3(ck.threads), ck.lds, stream, ca);
         plane_chirp(j, ga.q1y, ga.q1x);
         ga.first = j == 0;
         ga.last = j == P - 1;
@@ -506,18 +526,19 @@ hg_status grad_run(const hg_plan* planes, int P, const float* target_amp, float*
         const int nj = j + 1 < P ? j + 1 : (k + 1 < states ? 0 : -1);
         if (nj >= 0) {
           plane_chirp(nj, ga.qny, ga.qnx);
-          hipLaunchKernelGGL(rk.grad_row_next, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+          hipLaunchKernelGGL(rk.grad_row_next, rows, dim3(rk.threads), rk.lds, stream, ga);
           started = true;
         } else {
-          hipLaunchKernelGGL(rk.grad_row, dim3(p0->row_blocks), dim3(rk.threads), rk.lds, stream, ga);
+          hipLaunchKernelGGL(rk.grad_row, rows, dim3(rk.threads), rk.lds, stream, ga);
         }
       } else if (loss) {
-        hipLaunchKernelGGL(ck.gs_col_nmse, dim3(p0->col_blocks), dim3(ck.threads), ck.lds, stream, ca);
+        hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
       }
     }
     if (loss && (k - chunk0 == kNmseChunk - 1 || k == states - 1)) {
-      hipLaunchKernelGGL(k_loss_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
-                         (const float*)partials, p0->col_blocks, P, (const Scalars*)sc, loss + chunk0);
+      hipLaunchKernelGGL(k_loss_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
+                         (const float*)partials, p0->col_blocks, P, (const Scalars*)sc, loss + chunk0,
+                         L.partial_stride, loss_stride);
       chunk0 = k + 1;
     }
   }
@@ -599,7 +620,8 @@ hg_status gs_run_angular(hg_plan p, const float* target_amp, const float* illumi
 // axis (batch = 1: one hologram).  Every pass is one launch over all items
 // (grid.y = batch item), so a batch of small holograms fills the GPU.
 hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* illumination, float* phase,
-                 uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
+                 uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream,
+                 const uint8_t* window = nullptr) {
   const int W = p->desc.width, H = p->desc.height;
   const size_t n = npix(p);
   const WsLayout L = ws_layout(p, batch);
@@ -631,7 +653,7 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   const uint32_t tiled_n = (uint32_t)L.target_stride;
   for (int b = 0; b < batch; ++b)
     hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, target_amp + (size_t)b * n,
-                       w.target + (size_t)b * L.target_stride, H, W, cols, tiled_n);
+                       w.target + (size_t)b * L.target_stride, H, W, cols, tiled_n, window);
 
   GsColArgs ca{};
   ca.ft = p->ft;
@@ -644,6 +666,7 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   ca.twr = p->tw_col[1];
   ca.px = (uint32_t)field_elems(p);
   ca.target_stride = (uint32_t)L.target_stride;
+  ca.sc_stride = 1;
   ca.partial_stride = (uint32_t)L.partial_stride;
 
   const int mode = p->levels == 0 ? GS_CONT
@@ -651,8 +674,12 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   // steady-state kernel unless the pass needs illumination or produces outputs
   void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
 
-  if (nmse)
-    for (int b = 0; b < batch; ++b) enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream);
+  // a window needs its target scale even without the error trace
+  if (nmse || window)
+    for (int b = 0; b < batch; ++b)
+      enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream, window);
+  void (*col_hot)(GsColArgs) = window ? ck.gs_col_win : ck.gs_col;
+  void (*col_last)(GsColArgs) = window ? ck.gs_col_win_nmse : ck.gs_col_nmse;
 
   const dim3 rows(p->row_blocks, batch), tiles(p->col_blocks, batch);
   ra.phase0 = phase;
@@ -664,16 +691,21 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   for (int k = 0; k <= iterations; ++k) {
     const bool last = k == iterations;
     if (last && !nmse) break;
-    ca.partials = nmse ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
+    ca.partials = (nmse && !window) ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
+    ca.wpartials = (nmse && window) ? w.wpartials + (size_t)(k - chunk0) * 3 * p->col_blocks : nullptr;
     if (last) {
-      hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
+      hipLaunchKernelGGL(col_last, tiles, dim3(ck.threads), ck.lds, stream, ca);
     } else {
-      launch(p, HG_KERNEL_GS_REPLAY, stream, ck.gs_col, tiles, ck.threads, ck.lds, ca);
+      launch(p, HG_KERNEL_GS_REPLAY, stream, col_hot, tiles, ck.threads, ck.lds, ca);
     }
     if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
-      hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
-                         (const float*)w.partials, p->col_blocks, (const Scalars*)w.sc, nmse + chunk0,
-                         L.partial_stride, (size_t)iterations + 1);
+      if (window)
+        hipLaunchKernelGGL(k_window_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
+                           (const double*)w.wpartials, p->col_blocks, (const Scalars*)w.sc, n, nmse + chunk0);
+      else
+        hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
+                           (const float*)w.partials, p->col_blocks, (const Scalars*)w.sc, nmse + chunk0,
+                           L.partial_stride, (size_t)iterations + 1);
       chunk0 = k + 1;
     }
     if (last) break;
@@ -907,6 +939,17 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
   if (p->desc.propagation == HG_ANGULAR)
     return gs_run_angular(p, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
   return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
+}
+
+hg_status hg_gs_iterate_window(hg_plan p, const float* target_amp, const uint8_t* window, const float* illumination,
+                               float* phase, uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                               hipStream_t stream) {
+  const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
+  if (st != HG_OK) return st;
+  if (!window) return fail(HG_ERR_INVALID_ARGUMENT, "window is NULL");
+  if (p->desc.propagation == HG_ANGULAR)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_window takes HG_FOURIER or HG_FRESNEL plans");
+  return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream, window);
 }
 
 hg_status hg_gs_iterate_noalloc(hg_plan p, const float* target_amp, const float* illumination, float* phase,
@@ -1272,31 +1315,45 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
 }
 
 size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes) {
-  if (!plan || n_planes < 1 || n_planes > kMaxPlanes) return 0;
-  return grad_layout(plan, n_planes).total;
+  return hg_grad_workspace_bytes_batched(plan, n_planes, 1);
 }
 
-hg_status hg_grad(const hg_plan* planes, int32_t n_planes, const float* target_amp, const float* phase, float* grad,
-                  float* loss, void* workspace, hipStream_t stream) {
+size_t hg_grad_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch) {
+  if (!plan || n_planes < 1 || n_planes > kMaxPlanes || batch < 1 || batch > 65535) return 0;
+  return grad_layout(plan, n_planes, batch).total;
+}
+
+namespace {
+
+hg_status grad_validate(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                        void* workspace) {
   hg_status st = validate_planes(planes, n_planes);
   if (st != HG_OK) return st;
   if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
+  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
+  if ((size_t)batch * field_elems(planes[0]) > (size_t)UINT32_MAX)
+    return fail(HG_ERR_INVALID_ARGUMENT, "batch * height * (padded) width must be below 2^32");
+  return HG_OK;
+}
+
+hg_status grad_eval(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                    const float* phase, float* grad, float* loss, void* workspace, hipStream_t stream) {
+  hg_status st = grad_validate(planes, n_planes, batch, target_amp, workspace);
+  if (st != HG_OK) return st;
   if (!phase) return fail(HG_ERR_INVALID_ARGUMENT, "phase is NULL");
-  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (!grad && !loss) return HG_OK;
-  // one evaluation: the phase is only read (no Adam state)
-  return grad_run(planes, n_planes, target_amp, const_cast<float*>(phase), grad, nullptr, nullptr, grad ? 1 : 0,
-                  1, 0.f, 0.f, 0.f, 0.f, loss, grad == nullptr, workspace, stream);
+  // one evaluation: the phase is only read (no Adam state); one loss per problem
+  return grad_run(planes, n_planes, batch, target_amp, const_cast<float*>(phase), grad, nullptr, nullptr,
+                  grad ? 1 : 0, 1, 0.f, 0.f, 0.f, 0.f, loss, 1, grad == nullptr, workspace, stream);
 }
 
-hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* target_amp, float* phase, float* adam_m,
-                       float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1, float beta2, float eps,
-                       float* loss, void* workspace, hipStream_t stream) {
-  hg_status st = validate_planes(planes, n_planes);
+hg_status grad_adam(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp, float* phase,
+                    float* adam_m, float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1,
+                    float beta2, float eps, float* loss, void* workspace, hipStream_t stream) {
+  hg_status st = grad_validate(planes, n_planes, batch, target_amp, workspace);
   if (st != HG_OK) return st;
-  if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
   if (!phase || !adam_m || !adam_v) return fail(HG_ERR_INVALID_ARGUMENT, "phase/adam_m/adam_v is NULL");
-  if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (steps < 0) return fail(HG_ERR_INVALID_ARGUMENT, "steps must be >= 0");
   if (first_step < 1) return fail(HG_ERR_INVALID_ARGUMENT, "first_step must be >= 1");
   if (!(std::isfinite(lr) && lr > 0.f)) return fail(HG_ERR_INVALID_ARGUMENT, "lr must be finite and > 0");
@@ -1304,8 +1361,35 @@ hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* tar
     return fail(HG_ERR_INVALID_ARGUMENT, "beta1 and beta2 must be in [0, 1)");
   if (!(std::isfinite(eps) && eps > 0.f)) return fail(HG_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
   if (steps == 0 && !loss) return HG_OK;
-  return grad_run(planes, n_planes, target_amp, phase, nullptr, adam_m, adam_v, steps, first_step, lr, beta1, beta2,
-                  eps, loss, loss != nullptr, workspace, stream);
+  return grad_run(planes, n_planes, batch, target_amp, phase, nullptr, adam_m, adam_v, steps, first_step, lr, beta1,
+                  beta2, eps, loss, (size_t)steps + 1, loss != nullptr, workspace, stream);
+}
+
+}  // namespace
+
+hg_status hg_grad(const hg_plan* planes, int32_t n_planes, const float* target_amp, const float* phase, float* grad,
+                  float* loss, void* workspace, hipStream_t stream) {
+  return grad_eval(planes, n_planes, 1, target_amp, phase, grad, loss, workspace, stream);
+}
+
+hg_status hg_grad_batched(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                          const float* phase, float* grad, float* loss, void* workspace, hipStream_t stream) {
+  return grad_eval(planes, n_planes, batch, target_amp, phase, grad, loss, workspace, stream);
+}
+
+hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* target_amp, float* phase, float* adam_m,
+                       float* adam_v, int32_t steps, int32_t first_step, float lr, float beta1, float beta2, float eps,
+                       float* loss, void* workspace, hipStream_t stream) {
+  return grad_adam(planes, n_planes, 1, target_amp, phase, adam_m, adam_v, steps, first_step, lr, beta1, beta2, eps,
+                   loss, workspace, stream);
+}
+
+hg_status hg_grad_adam_batched(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                               float* phase, float* adam_m, float* adam_v, int32_t steps, int32_t first_step,
+                               float lr, float beta1, float beta2, float eps, float* loss, void* workspace,
+                               hipStream_t stream) {
+  return grad_adam(planes, n_planes, batch, target_amp, phase, adam_m, adam_v, steps, first_step, lr, beta1, beta2,
+                   eps, loss, workspace, stream);
 }
 
 hg_status hg_timing_begin(hg_plan p, int32_t kernel, int32_t repeats) {

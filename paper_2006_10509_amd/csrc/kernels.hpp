@@ -55,6 +55,7 @@ struct Scalars {
   double denom;     // N_px^2 sum(T^4) / sum(T^2)^2 = N_px^2 sum (T_I / sum T_I)^2
   double sum_t2, sum_t4, sum_a2;
   float g;          // 2 a / denom: dNMSE/dI = g (a I - b T^2) for the gradient pass
+  float c;          // sqrt(sum I / sum T^2): the target scale of a signal window
 };
 
 // SLM constraint shared by the GS kernels.
@@ -259,7 +260,10 @@ struct RowTeam {
       team = threadIdx.x / P::T;
       t = threadIdx.x % P::T;
     }
-    int row = blockIdx.x * C::TEAMS + team;
+    // Tiled: neighbouring workgroups (whose rows share the field's cache
+    // lines when a tile row is narrower than a line) go to one XCD.
+    const int blk = (FT && ft) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int row = blk * C::TEAMS + team;
     if constexpr (!FT && P::T == 64) row = __builtin_amdgcn_readfirstlane(row);
     live = row < H;
     y = live ? row : H - 1;
@@ -326,10 +330,21 @@ extern __shared__ float2 hg_dyn_lds[];
 // kernels) one table of N complex values such as the Fresnel chirp q_x when it
 // is shared through LDS (see RowTable).
 // ---------------------------------------------------------------------------
+// Every kernel of a length shares one LDS reservation, sized by the twiddle
+// needs of the kernels that run both transform orders; one-order kernels
+// must fit inside it.
+template <class P, int THREADS>
+constexpr bool tw_fits_reservation() {
+  constexpr int both = PassTwiddles<P, THREADS, true, true>::LDS_WORDS;
+  return PassTwiddles<P, THREADS, true, false>::LDS_WORDS <= both &&
+         PassTwiddles<P, THREADS, false, true>::LDS_WORDS <= both;
+}
+
 template <int N>
 struct RowLds {
   using C = RowCfg<N>;
   using P = typename C::P;
+  static_assert(tw_fits_reservation<P, C::THREADS>(), "one-order twiddles exceed the LDS reservation");
   // a team's exchange region, padded to 4 mod 16 complex values so that the
   // interleaved teams of one wavefront start on different LDS banks
   static constexpr int TEAM = lds_len(N) + (20 - lds_len(N) % 16) % 16;
@@ -341,6 +356,7 @@ template <int N>
 struct ColLds {
   using C = ColCfg<N>;
   using P = typename C::P;
+  static_assert(tw_fits_reservation<P, C::THREADS>(), "one-order twiddles exceed the LDS reservation");
   static constexpr int TWF = C::C * lds_len(N);
   static constexpr int WORDS = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
 };
@@ -709,18 +725,52 @@ struct GsColArgs {
   float* partials;            // one float per workgroup for this state; null -> no NMSE
   const float2* tw;
   const float2* twr;
+  // signal window (k_gs_col<N, MODE, true>): per state the three sums
+  // [3][workgroups] of the windowed error (see k_gs_col)
+  double* wpartials;
   // batch strides of item blockIdx.y: field elements (tiled layout),
-  // tiled-target floats, partial floats (the Scalars advance by one per item)
-  uint32_t px, target_stride, partial_stride;
+  // tiled-target floats, Scalars, partial floats
+  uint32_t px, target_stride, sc_stride, partial_stride;
   int ft;                     // field layout (ColField)
   __device__ __forceinline__ void select_item() {
     const uint32_t b = blockIdx.y;
     field += b * px;
     target += b * target_stride;
-    sc += b;
+    sc += b * sc_stride;
     if (partials) partials += b * partial_stride;
   }
 };
+
+// Wavefront then workgroup sums of three doubles per thread, fixed order;
+// the totals are valid in thread 0.
+template <int THREADS>
+__device__ __forceinline__ void block_sum3_f64(double& x, double& y, double& z, double* red) {
+  static_assert(THREADS % 64 == 0, "whole wavefronts");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_xor(x, off, 64);
+    y += __shfl_xor(y, off, 64);
+    z += __shfl_xor(z, off, 64);
+  }
+  constexpr int NW = THREADS / 64;
+  if constexpr (NW > 1) {
+    if ((threadIdx.x & 63) == 0) {
+      red[3 * (threadIdx.x >> 6) + 0] = x;
+      red[3 * (threadIdx.x >> 6) + 1] = y;
+      red[3 * (threadIdx.x >> 6) + 2] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      x = y = z = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        x += red[3 * i + 0];
+        y += red[3 * i + 1];
+        z += red[3 * i + 2];
+      }
+    }
+  }
+}
 
 // Replay-plane pass of one state.  Column FFT -> R (the forward FFT2 of the
 // SLM field completes here); NMSE partial sum(d^2), d = a |R|^2 - b T^2; then
@@ -729,9 +779,16 @@ struct GsColArgs {
 //   COL_GRAD:    R' = dL/dconj(R) = g d R (Wirtinger derivative of the NMSE);
 // -> inverse column FFT (unscaled: with the inverse row FFT of the next pass
 // it is the adjoint F^H of the forward FFT2) -> field.
+// WIN (COL_NMSE, COL_REPLACE): a signal window, marked by negative values of
+// the tiled target (k_tile_target).  Inside, R' = c T R / |R| with the target
+// scale c; outside, R is kept.  The error is measured inside only, where sum I
+// is not known in advance, so each workgroup writes three sums instead of one,
+// with x = a |R|^2 and y = b T^2 (b from the window's sum T^2):
+// sum x, sum x^2 and sum x y, in FP64 (k_window_nmse_reduce combines them).
 enum { COL_NMSE = 0, COL_REPLACE = 1, COL_GRAD = 2 };
-template <int N, int MODE>
+template <int N, int MODE, bool WIN = false>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
+  static_assert(!WIN || MODE != COL_GRAD, "no signal window in the gradient pass");
   a.select_item();
   using C = ColCfg<N>;
   using P = typename C::P;
@@ -761,32 +818,68 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
   if constexpr (TW::USES_LDS) __syncthreads();
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
   float acc = 0.f;
-  const bool nm = a.partials != nullptr;
+  double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+  const bool nm = WIN ? (a.wpartials != nullptr) : (a.partials != nullptr);
   const bool scaled = nm || MODE == COL_GRAD;
   const float sa = scaled ? a.sc->a : 0.f;
   const float sb = scaled ? a.sc->b : 0.f;
   const float sg = MODE == COL_GRAD ? a.sc->g : 0.f;
-  for_layout<L1>(t, [&](int s, int) {
-    const float2 R = v[s];
-    const float tv = tgt[s];
-    const float I = cnorm(R);
-    const float d = fmaf(I, sa, -(tv * tv * sb));
-    acc = fmaf(d, d, acc);
-    if constexpr (MODE == COL_REPLACE) {
-      const float k = tv * rsqrtf(I);
-      v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(tv, 0.0f);
-    } else if constexpr (MODE == COL_GRAD) {
-      const float k = sg * d;
-      v[s] = make_float2(R.x * k, R.y * k);
-    }
-  });
-  if (nm) {
-    const float s = block_sum<C::THREADS>(live ? acc : 0.0f, red);
-    if (threadIdx.x == 0) a.partials[tile] = s;
+  if constexpr (WIN) {
+    const float sc = a.sc->c;
+    for_layout<L1>(t, [&](int s, int) {
+      const float2 R = v[s];
+      const float tv = tgt[s];
+      if (tv >= 0.0f) {
+        const float I = cnorm(R);
+        const double x = (double)(I * sa), y = (double)(tv * tv * sb);
+        w1 += x;
+        w2 = fma(x, x, w2);
+        w3 = fma(x, y, w3);
+        if constexpr (MODE == COL_REPLACE) {
+          const float ct = tv * sc;
+          const float k = ct * rsqrtf(I);
+          v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(ct, 0.0f);
+        }
+      }
+    });
+  } else {
+    for_layout<L1>(t, [&](int s, int) {
+      const float2 R = v[s];
+      const float tv = tgt[s];
+      const float I = cnorm(R);
+      const float d = fmaf(I, sa, -(tv * tv * sb));
+      acc = fmaf(d, d, acc);
+      if constexpr (MODE == COL_REPLACE) {
+        const float k = tv * rsqrtf(I);
+        v[s] = I > 0.0f ? make_float2(R.x * k, R.y * k) : make_float2(tv, 0.0f);
+      } else if constexpr (MODE == COL_GRAD) {
+        const float k = sg * d;
+        v[s] = make_float2(R.x * k, R.y * k);
+      }
+    });
   }
   if constexpr (BACK) {
     tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
     if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, f.at(y), v[s]); });
+  }
+  // The error's workgroup sum runs last, while the field stores drain: the
+  // replaced values do not depend on it, and its barrier and shuffles would
+  // otherwise sit between the two transforms.
+  if constexpr (WIN) {
+    if (nm) {
+      __shared__ double wred[3 * (C::THREADS / 64)];
+      if (!live) w1 = w2 = w3 = 0.0;
+      block_sum3_f64<C::THREADS>(w1, w2, w3, wred);
+      if (threadIdx.x == 0) {
+        const uint32_t nwg = gridDim.x;
+        a.wpartials[tile] = w1;
+        a.wpartials[nwg + tile] = w2;
+        a.wpartials[2 * nwg + tile] = w3;
+      }
+    }
+  } else if (nm) {
+    const float s = block_sum<C::THREADS>(live ? acc : 0.0f, red);
+    if (threadIdx.x == 0) a.partials[tile] = s;
   }
 }
 
@@ -812,6 +905,18 @@ struct GradRowArgs {
   const float2* qnx;
   const float2* tw;
   const float2* twr;
+  uint32_t px;             // batch: pixels per problem (row-order arrays)
+  uint32_t fpx;            // batch: field elements per problem
+  // Problem blockIdx.y of a launch over a batch of same-shape problems.
+  __device__ __forceinline__ void select_item() {
+    const uint32_t off = blockIdx.y * px;
+    field += blockIdx.y * fpx;
+    phase += off;
+    acc += off;
+    if (grad_out) grad_out += off;
+    if (m) m += off;
+    if (v) v += off;
+  }
 };
 
 // Inverse row FFT (completes G = F^H dL/dconj(U) of this plane) -> V = Q1
@@ -826,6 +931,7 @@ struct GradRowArgs {
 // separate start pass after its first.
 template <int N, bool NEXT>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) {
+  a.select_item();
   using C = RowCfg<N>;
   using P = typename C::P;
   using LL = RowLds<N>;
@@ -1238,6 +1344,8 @@ struct ColKernels {
   void (*prop_inv)(PropColArgs);
   void (*gs_col)(GsColArgs);
   void (*gs_col_nmse)(GsColArgs);
+  void (*gs_col_win)(GsColArgs);        // signal window
+  void (*gs_col_win_nmse)(GsColArgs);
   void (*grad_col)(GsColArgs);
   void (*ospr_b)(OsprColArgs);
   void (*ospr_b_pair)(OsprColArgs);
@@ -1298,7 +1406,7 @@ LengthEntry make_length_entry() {
   e.row.lds = sizeof(float2) * RowLds<N>::WORDS;
   e.row.ft = RowTeam<RowCfg<N>>::FT;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
-           k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
+           k_gs_col<N, COL_REPLACE, true>, k_gs_col<N, COL_NMSE, true>, k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
   using PR = typename RowCfg<N>::P;
   using PC = typename ColCfg<N>::P;

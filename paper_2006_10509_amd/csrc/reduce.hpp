@@ -13,9 +13,12 @@ namespace hg {
 
 // Target amplitude rearranged once per call for the column pass: FFT order
 // (T_f[ky][kx] = T[(ky + H/2) % H][(kx + W/2) % W]) and tiled so that the C
-// columns of one column workgroup form one contiguous [ky][c] block.
+// columns of one column workgroup form one contiguous [ky][c] block.  With a
+// signal window (centred, nonzero inside), pixels outside it get -1: the
+// windowed column pass reads the sign as the window.
 __global__ __launch_bounds__(256) void k_tile_target(const float* __restrict__ target, float* __restrict__ tiled,
-                                                     int H, int W, int C, uint32_t total) {
+                                                     int H, int W, int C, uint32_t total,
+                                                     const uint8_t* __restrict__ window = nullptr) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= total) return;
   const int c = i % C;
@@ -27,6 +30,7 @@ __global__ __launch_bounds__(256) void k_tile_target(const float* __restrict__ t
     const int ys = wrap_add_rt(ky, H / 2, H);
     const int xs = wrap_add_rt(x, W / 2, W);
     v = target[(size_t)ys * W + xs];
+    if (window && window[(size_t)ys * W + xs] == 0) v = -1.0f;
   }
   tiled[i] = v;
 }
@@ -52,14 +56,17 @@ __device__ __forceinline__ double block_sum_f64(double v, double* red) {
   return r;
 }
 
-// sum T^2, sum T^4, sum A^2 per workgroup (FP64), fixed order.
+// sum T^2, sum T^4, sum A^2 per workgroup (FP64), fixed order; with a
+// signal window (same order as the target, nonzero inside) the target sums
+// run over the window only.
 __global__ __launch_bounds__(STATS_THREADS) void k_stats_partial(const float* __restrict__ target,
                                                                  const float* __restrict__ illum,
-                                                                 size_t n, double* __restrict__ part) {
+                                                                 size_t n, double* __restrict__ part,
+                                                                 const uint8_t* __restrict__ window = nullptr) {
   __shared__ double red[STATS_THREADS];
   double t2 = 0.0, t4 = 0.0, a2 = 0.0;
   for (size_t i = (size_t)blockIdx.x * STATS_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * STATS_THREADS) {
-    const double tv = (double)target[i];
+    const double tv = (window && window[i] == 0) ? 0.0 : (double)target[i];
     const double q = tv * tv;
     t2 += q;
     t4 += q * q;
@@ -106,6 +113,34 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __r
     sc->b = (float)(npx / t2);
     sc->denom = npx * npx * t4 / (t2 * t2);
     sc->g = (float)(2.0 * (npx / s_i) / sc->denom);
+    sc->c = (float)sqrt(s_i / t2);
+  }
+}
+
+// Windowed NMSE of state blockIdx.x from the three per-workgroup sums of the
+// windowed column pass (sum x, sum x^2, sum x y; x = a I, y = b T^2, so that
+// sum_M y = N_px and sum_M y^2 = denom):
+//   NMSE = sum_M (x / S1 - y / N_px)^2 / sum_M (y / N_px)^2
+//        = 1 + (S2 / S1^2 - 2 S3 / (S1 N_px)) N_px^2 / denom,
+// 1 when no light reaches the window (S1 = 0).  Fixed order, FP64.
+__global__ __launch_bounds__(STATS_THREADS) void k_window_nmse_reduce(const double* __restrict__ wpartials, int nwg,
+                                                                      const Scalars* __restrict__ sc, size_t npx,
+                                                                      float* __restrict__ nmse) {
+  __shared__ double red[STATS_THREADS];
+  const double* p = wpartials + (size_t)blockIdx.x * 3 * nwg;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) {
+    s1 += p[i];
+    s2 += p[nwg + i];
+    s3 += p[2 * nwg + i];
+  }
+  s1 = block_sum_f64<STATS_THREADS>(s1, red);
+  s2 = block_sum_f64<STATS_THREADS>(s2, red);
+  s3 = block_sum_f64<STATS_THREADS>(s3, red);
+  if (threadIdx.x == 0) {
+    const double n = (double)npx;
+    const double e = s1 > 0.0 ? 1.0 + (s2 / (s1 * s1) - 2.0 * s3 / (s1 * n)) * n * n / sc->denom : 1.0;
+    nmse[blockIdx.x] = (float)e;
   }
 }
 
@@ -142,10 +177,16 @@ __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce_planes(const floa
 
 // loss[k] = sum_j (sum_wg partials[k][j][wg]) / denom_j: the summed NMSE of the
 // `planes` replay planes of state k, one workgroup per state, fixed order.
+// Batch item blockIdx.y takes its partials, Scalars and losses at the given
+// strides.
 __global__ __launch_bounds__(STATS_THREADS) void k_loss_reduce(const float* __restrict__ partials, int nwg,
                                                                int planes, const Scalars* __restrict__ sc,
-                                                               float* __restrict__ loss) {
+                                                               float* __restrict__ loss, size_t partial_stride,
+                                                               size_t loss_stride) {
   __shared__ double red[STATS_THREADS];
+  partials += blockIdx.y * partial_stride;
+  sc += blockIdx.y * (size_t)planes;
+  loss += blockIdx.y * loss_stride;
   double total = 0.0;
   for (int j = 0; j < planes; ++j) {
     const float* p = partials + ((size_t)blockIdx.x * planes + j) * nwg;

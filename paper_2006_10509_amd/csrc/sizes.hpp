@@ -51,7 +51,7 @@ HG_ROW_CFG(64,    32,     8,  0,   8, 8)
 HG_ROW_CFG(128,   16,    16,  0,   8, 2, 8)
 HG_ROW_CFG(256,   16,    16,  0,   16, 16)
 HG_ROW_CFG(512,   2,    64,  0,   8, 8, 8)
-HG_ROW_CFG(1024,   2,   128,  8,   8, 4, 4, 8)
+HG_ROW_CFG(1024,   2,   128,  4,   8, 4, 4, 8)
 HG_ROW_CFG(2048,   2,   128,  8,   16, 8, 16)
 HG_ROW_CFG(4096,   2,   128,  0,   16, 16, 16)
 HG_ROW_CFG(24,    32,     8,  0,   8, 3)
@@ -60,6 +60,11 @@ HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
 HG_ROW_CFG(120,   16,    16,  0,   8, 3, 5)
 HG_ROW_CFG(1080,   4,    64,  0,   8, 3, 3, 3, 5)
 HG_ROW_CFG(1920,   4,   128,  0,   16, 3, 5, 8)
+HG_ROW_CFG(1280,   2,   128,  0,   16, 5, 16)
+HG_ROW_CFG(1536,   2,   128,  0,   8, 8, 8, 3)
+HG_ROW_CFG(2160,   4,   144,  0,   16, 3, 3, 3, 5)
+HG_ROW_CFG(3840,   2,   256,  0,   16, 16, 3, 5)
+HG_ROW_CFG(8192,   1,  1024,  0,   8, 8, 8, 8, 2)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
@@ -68,8 +73,8 @@ HG_COL_CFG(64,    16,     8,   8, 8)
 HG_COL_CFG(128,   16,    16,   8, 2, 8)
 HG_COL_CFG(256,    8,    16,   16, 16)
 HG_COL_CFG(512,   8,    64,   8, 8, 8)
-HG_COL_CFG(1024,   4,   128,   8, 4, 4, 8)
-HG_COL_CFG(2048,   8,    64,   16, 8, 16)
+HG_COL_CFG(1024,   2,   128,   8, 4, 4, 8)
+HG_COL_CFG(2048,   4,   128,   16, 8, 16)
 HG_COL_CFG(4096,   2,   128,   16, 16, 16)
 HG_COL_CFG(24,    16,     8,   8, 3)
 HG_COL_CFG(60,    16,    16,   4, 3, 5)
@@ -77,10 +82,16 @@ HG_COL_CFG(90,    16,    16,   2, 3, 3, 5)
 HG_COL_CFG(120,   16,    16,   8, 3, 5)
 HG_COL_CFG(1080,   8,   120,   8, 3, 3, 3, 5)
 HG_COL_CFG(1920,   4,    64,   16, 8, 3, 5)
+HG_COL_CFG(1280,   4,   128,   16, 5, 16)
+HG_COL_CFG(1536,   4,   128,   8, 8, 8, 3)
+HG_COL_CFG(2160,   4,   144,   16, 3, 3, 3, 5)
+HG_COL_CFG(3840,   2,   256,   16, 16, 3, 5)
+HG_COL_CFG(8192,   2,   256,   8, 8, 8, 16)
 
 // X-macro over every compiled length (used for host dispatch tables).
 #define HG_FOR_EACH_LENGTH(X) \
   X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) \
-  X(24) X(60) X(90) X(120) X(1080) X(1920)
+  X(24) X(60) X(90) X(120) X(1080) X(1920) \
+  X(1280) X(1536) X(2160) X(3840) X(8192)
 
 }  // namespace hg

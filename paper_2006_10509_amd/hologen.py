@@ -40,11 +40,12 @@ HG_KERNEL_PROP_ROW = 6
 HG_KERNEL_PROP_COL = 7
 
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
-            "hg_propagate", "hg_gs_iterate", "hg_gs_iterate_noalloc", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
+            "hg_propagate", "hg_gs_iterate", "hg_gs_iterate_window", "hg_gs_iterate_noalloc", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
             "hg_multiplane_workspace_bytes", "hg_gs_multiplane",
             "hg_ospr", "hg_ospr_pairs", "hg_search_workspace_bytes", "hg_pixel_search",
-            "hg_grad_workspace_bytes", "hg_grad",
-            "hg_grad_adam", "hg_timing_begin", "hg_timing_end", "hg_error")
+            "hg_grad_workspace_bytes", "hg_grad", "hg_grad_adam",
+            "hg_grad_workspace_bytes_batched", "hg_grad_batched", "hg_grad_adam_batched",
+            "hg_timing_begin", "hg_timing_end", "hg_error")
 
 
 class hg_plan_desc(ctypes.Structure):
@@ -91,6 +92,8 @@ def library() -> ctypes.CDLL:
     lib.hg_propagate.restype = i32
     lib.hg_gs_iterate.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.hg_gs_iterate.restype = i32
+    lib.hg_gs_iterate_window.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.hg_gs_iterate_window.restype = i32
     lib.hg_gs_iterate_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
     lib.hg_gs_iterate_noalloc.restype = i32
     lib.hg_workspace_bytes_batched.argtypes = [vp, i32]
@@ -117,6 +120,13 @@ def library() -> ctypes.CDLL:
     lib.hg_grad_adam.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, i32, i32, f32, f32, f32, f32,
                                  vp, vp, vp]
     lib.hg_grad_adam.restype = i32
+    lib.hg_grad_workspace_bytes_batched.argtypes = [vp, i32, i32]
+    lib.hg_grad_workspace_bytes_batched.restype = sz
+    lib.hg_grad_batched.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.hg_grad_batched.restype = i32
+    lib.hg_grad_adam_batched.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, i32, i32, f32, f32, f32,
+                                         f32, vp, vp, vp]
+    lib.hg_grad_adam_batched.restype = i32
     lib.hg_timing_begin.argtypes = [vp, i32, i32]
     lib.hg_timing_begin.restype = i32
     lib.hg_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -247,6 +257,22 @@ def hg_gs_iterate(plan: Plan, target_amp, phase, iterations: int, workspace,
     shape = (plan.height, plan.width)
     _check(library().hg_gs_iterate(
         plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape, "illumination", optional=True),
+        _ptr(phase, torch.float32, shape, "phase"),
+        _ptr(levels, torch.uint8, shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (iterations + 1,), "nmse", optional=True),
+        int(iterations), _workspace(workspace, plan.workspace_bytes()), _stream(stream)))
+
+
+def hg_gs_iterate_window(plan: Plan, target_amp, window, phase, iterations: int, workspace,
+                         illumination=None, levels=None, nmse=None, stream=None) -> None:
+    """Signal-window GS: ``window`` [H, W] uint8, centred like the target,
+    nonzero inside; ``phase`` in place as in hg_gs_iterate."""
+    import torch
+    shape = (plan.height, plan.width)
+    _check(library().hg_gs_iterate_window(
+        plan.handle, _ptr(target_amp, torch.float32, shape, "target_amp"),
+        _ptr(window, torch.uint8, shape, "window"),
         _ptr(illumination, torch.float32, shape, "illumination", optional=True),
         _ptr(phase, torch.float32, shape, "phase"),
         _ptr(levels, torch.uint8, shape, "levels", optional=True),
@@ -420,6 +446,48 @@ def hg_grad_adam(planes, target_amp, phase, adam_m, adam_v, steps: int, workspac
         float(betas[0]), float(betas[1]), float(eps),
         _ptr(loss, torch.float32, (int(steps) + 1,), "loss", optional=True),
         _workspace(workspace, grad_workspace_bytes(planes)), _stream(stream)))
+
+
+def grad_workspace_bytes_batched(planes, batch: int) -> int:
+    planes, _ = _plans(planes)
+    return int(library().hg_grad_workspace_bytes_batched(planes[0].handle, len(planes), int(batch)))
+
+
+def grad_workspace_batched(planes, batch: int, device="cuda"):
+    import torch
+    return torch.empty(grad_workspace_bytes_batched(planes, batch), dtype=torch.uint8, device=device)
+
+
+def hg_grad_batched(planes, target_amp, phase, workspace, grad=None, loss=None, stream=None) -> None:
+    """hg_grad on a batch: ``target_amp`` [B, n_planes, H, W], ``phase`` and
+    ``grad`` [B, H, W], ``loss`` [B]."""
+    import torch
+    planes, arr = _plans(planes)
+    shape = (planes[0].height, planes[0].width)
+    b = int(phase.shape[0]) if phase is not None and phase.dim() == 3 else -1
+    _check(library().hg_grad_batched(
+        arr, len(planes), b, _ptr(target_amp, torch.float32, (b, len(planes)) + shape, "target_amp"),
+        _ptr(phase, torch.float32, (b,) + shape, "phase"),
+        _ptr(grad, torch.float32, (b,) + shape, "grad", optional=True),
+        _ptr(loss, torch.float32, (b,), "loss", optional=True),
+        _workspace(workspace, grad_workspace_bytes_batched(planes, max(b, 1))), _stream(stream)))
+
+
+def hg_grad_adam_batched(planes, target_amp, phase, adam_m, adam_v, steps: int, workspace, first_step: int = 1,
+                         lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8, loss=None, stream=None) -> None:
+    """hg_grad_adam on a batch: ``target_amp`` [B, n_planes, H, W], ``phase``,
+    ``adam_m``, ``adam_v`` [B, H, W], ``loss`` [B, steps + 1] or None."""
+    import torch
+    planes, arr = _plans(planes)
+    shape = (planes[0].height, planes[0].width)
+    b = int(phase.shape[0]) if phase is not None and phase.dim() == 3 else -1
+    _check(library().hg_grad_adam_batched(
+        arr, len(planes), b, _ptr(target_amp, torch.float32, (b, len(planes)) + shape, "target_amp"),
+        _ptr(phase, torch.float32, (b,) + shape, "phase"), _ptr(adam_m, torch.float32, (b,) + shape, "adam_m"),
+        _ptr(adam_v, torch.float32, (b,) + shape, "adam_v"), int(steps), int(first_step), float(lr),
+        float(betas[0]), float(betas[1]), float(eps),
+        _ptr(loss, torch.float32, (b, int(steps) + 1), "loss", optional=True),
+        _workspace(workspace, grad_workspace_bytes_batched(planes, max(b, 1))), _stream(stream)))
 
 
 _LOSS_FN = None

@@ -89,7 +89,7 @@ def test_error_strings():
 
 
 def test_supported_lengths():
-    for n in (16, 256, 1024, 2048, 4096, 1080, 1920, 90, 120):
+    for n in (16, 256, 1024, 2048, 4096, 1080, 1920, 90, 120, 1280, 1536, 2160, 3840, 8192):
         assert hg.hg_length_supported(n)
-    for n in (0, 1, 7, 1000, 8191):
+    for n in (0, 1, 7, 1000, 8191, 16384):
         assert not hg.hg_length_supported(n)

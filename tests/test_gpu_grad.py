@@ -186,3 +186,65 @@ def test_argument_validation():
         run_adam(planes, targets, phi, 3, first=0)
     with pytest.raises(ValueError):
         hg.hg_grad(planes, dev(targets), dev(phi), ws[:16], loss=torch.empty(1, device="cuda"))
+
+
+# ---------------------------------------------------------------------------
+# batched problems (hg_grad_batched, hg_grad_adam_batched)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("h,w,distances,batch", [
+    (256, 256, [0.40, 0.45, 0.50], 3),
+    (1024, 1024, [0.40, 0.45, 0.50], 2),
+    (90, 120, [None, 0.5], 4),
+])
+def test_batched_problems_are_the_single_calls_bitwise(h, w, distances, batch):
+    """Every problem of a batched Adam run (phase, both moments, loss curve)
+    and of a batched evaluation (loss, gradient) is bitwise the single-problem
+    call; problem 0 of the evaluation also against the oracle."""
+    torch = torch_mod()
+    print(f"grad batched {h}x{w} planes={distances} batch={batch}", flush=True)
+    planes, dicts = make_planes(h, w, distances)
+    probs = [problem(h, w, len(distances), 40 + 7 * b) for b in range(batch)]
+    tb = dev(np.stack([t for t, _ in probs]))
+    pb = dev(np.stack([p for _, p in probs]))
+    steps = 6
+    # batched Adam
+    ph = pb.clone()
+    m = torch.zeros_like(ph)
+    v = torch.zeros_like(ph)
+    loss = torch.empty((batch, steps + 1), dtype=torch.float32, device="cuda")
+    hg.hg_grad_adam_batched(planes, tb, ph, m, v, steps, hg.grad_workspace_batched(planes, batch), loss=loss)
+    # batched evaluation
+    g = torch.empty((batch, h, w), dtype=torch.float32, device="cuda")
+    gl = torch.empty(batch, dtype=torch.float32, device="cuda")
+    hg.hg_grad_batched(planes, tb, pb, hg.grad_workspace_batched(planes, batch), grad=g, loss=gl)
+    ws = hg.grad_workspace(planes)
+    for b in range(batch):
+        p1 = pb[b].clone()
+        m1 = torch.zeros_like(p1)
+        v1 = torch.zeros_like(p1)
+        l1 = torch.empty(steps + 1, dtype=torch.float32, device="cuda")
+        hg.hg_grad_adam(planes, tb[b].contiguous(), p1, m1, v1, steps, ws, loss=l1)
+        g1 = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        gl1 = torch.empty(1, dtype=torch.float32, device="cuda")
+        hg.hg_grad(planes, tb[b].contiguous(), pb[b].contiguous(), ws, grad=g1, loss=gl1)
+        torch.cuda.synchronize()
+        assert torch.equal(ph[b], p1) and torch.equal(m[b], m1) and torch.equal(v[b], v1), b
+        assert torch.equal(loss[b], l1), b
+        assert torch.equal(g[b], g1) and torch.equal(gl[b:b + 1], gl1), b
+    t0, p0 = probs[0]
+    ref_loss, ref_g, _ = oracle.loss_and_gradient(p0.astype(np.float64), list(t0.astype(np.float64)), dicts)
+    assert abs(float(host(gl)[0]) - ref_loss) <= 1e-4 * ref_loss
+    assert rel_l2(host(g)[0], ref_g) <= 1e-4
+
+
+def test_batched_gradient_rejects_bad_batches():
+    planes, _ = make_planes(64, 64, [0.5])
+    assert hg.library().hg_grad_workspace_bytes_batched(planes[0].handle, 1, 0) == 0
+    torch = torch_mod()
+    t = torch.ones((1, 1, 64, 64), dtype=torch.float32, device="cuda")
+    p = torch.zeros((1, 64, 64), dtype=torch.float32, device="cuda")
+    import ctypes
+    arr = (ctypes.c_void_p * 1)(planes[0].handle)
+    ws = hg.grad_workspace_batched(planes, 1)
+    st = hg.library().hg_grad_batched(arr, 1, 0, t.data_ptr(), p.data_ptr(), None, p.data_ptr(), ws.data_ptr(), None)
+    assert st == hg.HG_ERR_INVALID_ARGUMENT

@@ -188,6 +188,16 @@ def test_gs_fresnel_1024_L8_first_10_iterations():
     (1080, 1024, 8, True, 3),
     (1024, 2048, 4, False, 2),
     (4096, 1024, 0, False, 1),
+    # the lengths of SLM resolutions 1280 x 1024, 1536, 2160 x 3840 and the 8192 transform
+    (1024, 1280, 8, True, 3),
+    (1536, 1280, 4, False, 3),
+    (1280, 1536, 0, True, 3),
+    (2160, 64, 8, True, 3),
+    (64, 3840, 4, False, 3),
+    (3840, 60, 8, False, 3),
+    (2160, 3840, 0, False, 2),
+    (8192, 16, 8, True, 3),
+    (16, 8192, 4, False, 3),
 ])
 def test_gs_shapes_and_modes(h, w, levels, fresnel, iters):
     print(f"gs {h}x{w} L={levels} fresnel={fresnel} it={iters}", flush=True)

@@ -14,7 +14,9 @@ TOL = 1e-5
 OPTICS = dict(wavelength=532e-9, pixel_pitch=8e-6, distance=0.5)
 
 SHAPES = [(16, 16), (32, 64), (24, 60), (90, 120), (120, 90), (256, 256), (128, 512),
-          (1024, 1024), (2048, 2048), (1080, 1920), (60, 4096), (4096, 24)]
+          (1024, 1024), (2048, 2048), (1080, 1920), (60, 4096), (4096, 24),
+          # SLM resolutions 1280 x 1024 / 1536 / 2160 x 3840 and the 8192 transform
+          (1024, 1280), (1280, 1536), (1536, 1280), (2160, 3840), (3840, 60), (16, 8192), (8192, 16)]
 
 
 def run(plan, x, direction, inplace=False):
@@ -96,3 +98,37 @@ def test_gaussian_beam_closed_form_on_gpu():
     zr = np.pi * w0 ** 2 / lam
     ref = np.exp(2j * np.pi * np.mod(z / lam, 1.0)) / (1 + 1j * z / zr) * np.exp(1j * a * b * r2 / (a - 1j * b))
     assert rel_l2(uz, ref) <= TOL
+
+
+def test_8192_full_size_closed_forms():
+    """8192 x 8192, past the 256 MiB last-level cache: the forward transform
+    of a delta on sampled rows against its closed form, of a plane wave
+    (one bin of height H W, zero elsewhere) everywhere, and the inverse of the
+    plane wave's spectrum back to the plane wave."""
+    torch = torch_mod()
+    h = w = 8192
+    print("fourier propagate 8192x8192 closed forms", flush=True)
+    plan = hg.Plan(w, h)
+    ws = plan.workspace()
+    x = torch.zeros((h, w), dtype=torch.complex64, device="cuda")
+    x[3, 17] = 1.0
+    out = torch.empty_like(x)
+    hg.hg_propagate(plan, x, out, hg.HG_FORWARD, ws)
+    rows = np.array([0, 1, 2, 3, 4095, 4096, 8191] + list(np.random.default_rng(8).integers(0, h, 9)))
+    got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    l = np.arange(w)[None, :]
+    ref = np.exp(-2j * np.pi * (np.mod(3 * rows[:, None], h) / h + np.mod(17 * l, w) / w))
+    assert np.abs(got - ref).max() <= 1e-5
+    m = torch.arange(h, device="cuda", dtype=torch.float64)[:, None]
+    n = torch.arange(w, device="cuda", dtype=torch.float64)[None, :]
+    ang = 2 * np.pi * (torch.remainder(5 * m, h) / h + torch.remainder(300 * n, w) / w)
+    pw = torch.polar(torch.ones_like(ang), ang).to(torch.complex64)
+    del ang
+    hg.hg_propagate(plan, pw, out, hg.HG_FORWARD, ws)
+    err = out.clone()
+    err[5, 300] -= h * w
+    assert float(err.abs().max()) <= 1e-5 * h * w
+    back = torch.empty_like(out)
+    hg.hg_propagate(plan, out, back, hg.HG_INVERSE, ws)
+    rel = float(torch.linalg.vector_norm(back - pw) / torch.linalg.vector_norm(pw))
+    assert rel <= TOL, rel
