@@ -97,6 +97,13 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->col.prop_inv, e->col.lds));
   chk(allow_lds(e->col.gs_col, e->col.lds));
   chk(allow_lds(e->col.gs_col_nmse, e->col.lds));
+  chk(allow_lds(e->col.gs_col_win, e->col.lds));
+  chk(allow_lds(e->col.gs_col_win_nmse, e->col.lds));
+  if (e->col_wide.cols) {
+    chk(allow_lds(e->col_wide.gs_col, e->col_wide.lds));
+    chk(allow_lds(e->col_wide.gs_col_nmse, e->col_wide.lds));
+    chk(allow_lds(e->col_wide.grad_col, e->col_wide.lds));
+  }
   chk(allow_lds(e->col.ospr_b, e->col.lds));
   chk(allow_lds(e->col.ospr_b_pair, e->col.lds));
   chk(allow_lds(e->row.grad_row, e->row.lds));
@@ -169,6 +176,13 @@ struct hg_plan_s {
   float2* unit_x = nullptr;  // exp(-2 pi i k / W), k < W
   int levels = 0;           // quantiser levels used by GS (0 = continuous)
   int row_blocks = 0, col_blocks = 0;
+  // batched column configuration: used when wide_ok (W a multiple of its
+  // column count, which also divides the field's tile width)
+  bool wide_ok = false;
+  int col_blocks_wide = 0;
+  // per-column error partials of one state: the padded width of the widest
+  // column configuration
+  int col_slots = 0;
   int ft = 0;              // GS-family field layout: 0 row order, else column tile width
   size_t ws_bytes = 0;     // workspace of one hologram (ws_layout(p, 1).total)
   std::vector<void*> allocations;
@@ -325,17 +339,17 @@ size_t field_elems(hg_plan p) {
 
 WsLayout ws_layout(hg_plan p, int batch) {
   const size_t n = field_elems(p);
-  const int nwg = p->row_blocks > p->col_blocks ? p->row_blocks : p->col_blocks;
+  const int nwg = p->row_blocks > p->col_slots ? p->row_blocks : p->col_slots;
   WsLayout L{};
   L.partial_stride = (size_t)kNmseChunk * nwg;
-  L.target_stride = (size_t)p->col_blocks * p->col->col.cols * p->desc.height;
+  L.target_stride = (size_t)p->col_slots * p->desc.height;
   L.sc = align_up((size_t)batch * n * sizeof(float2));
   L.stats = L.sc + align_up((size_t)batch * sizeof(Scalars));
   L.partials = L.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   L.target = L.partials + align_up((size_t)batch * L.partial_stride * sizeof(float));
   L.wpartials = L.target + align_up((size_t)batch * L.target_stride * sizeof(float));
   // signal window (one hologram): three FP64 sums per column workgroup and state
-  L.total = L.wpartials + align_up((size_t)kNmseChunk * 3 * p->col_blocks * sizeof(double));
+  L.total = L.wpartials + align_up((size_t)kNmseChunk * 3 * p->col_slots * sizeof(double));
   return L;
 }
 
@@ -377,6 +391,28 @@ void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const flo
                      intensity_sum, a2_scale, out);
 }
 
+// Column-pass configuration of a GS-family launch over `batch` holograms or
+// problems: the batched one (ColCfgWide) when the length has one that fits
+// the plan, else the single-hologram one.  Both write the error partials of
+// a state per column (slots = padded width) in the same order.
+struct ColLaunch {
+  void (*gs_col)(GsColArgs);
+  void (*gs_col_nmse)(GsColArgs);
+  void (*grad_col)(GsColArgs);
+  int cols, blocks, threads;
+  size_t lds;
+  int slots() const { return cols * blocks; }
+};
+
+ColLaunch col_launch(hg_plan p, int batch) {
+  if (batch > 1 && p->wide_ok) {
+    const ColWideKernels& w = p->col->col_wide;
+    return {w.gs_col, w.gs_col_nmse, w.grad_col, w.cols, p->col_blocks_wide, w.threads, w.lds};
+  }
+  const ColKernels& c = p->col->col;
+  return {c.gs_col, c.gs_col_nmse, c.grad_col, c.cols, p->col_blocks, c.threads, c.lds};
+}
+
 // Workspace of the gradient method for `batch` problems of `planes` replay
 // planes each: fields [batch] | dL/dphi accumulators [batch][H][W] | Scalars
 // [batch][planes] | stats | loss partials [batch][kNmseChunk states][planes]
@@ -390,13 +426,13 @@ struct GradLayout {
 GradLayout grad_layout(hg_plan p, int planes, int batch = 1) {
   const size_t n = npix(p);
   GradLayout g{};
-  g.partial_stride = (size_t)kNmseChunk * planes * p->col_blocks;
+  g.partial_stride = (size_t)kNmseChunk * planes * p->col_slots;
   g.acc = align_up((size_t)batch * field_elems(p) * sizeof(float2));
   g.sc = g.acc + align_up((size_t)batch * n * sizeof(float));
   g.stats = g.sc + align_up((size_t)batch * planes * sizeof(Scalars));
   g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   g.target = g.partials + align_up((size_t)batch * g.partial_stride * sizeof(float));
-  g.target_stride = align_up((size_t)p->col_blocks * p->col->col.cols * p->desc.height * sizeof(float));
+  g.target_stride = align_up((size_t)p->col_slots * p->desc.height * sizeof(float));
   g.total = g.target + (size_t)batch * planes * g.target_stride;
   return g;
 }
@@ -436,9 +472,9 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
   double* stats = reinterpret_cast<double*>(ws + L.stats);
   float* partials = reinterpret_cast<float*>(ws + L.partials);
   const RowKernels& rk = p0->row->row;
-  const ColKernels& ck = p0->col->col;
-  const int cols = ck.cols;
-  const uint32_t tiled_n = (uint32_t)p0->col_blocks * cols * H;
+  const ColLaunch cl = col_launch(p0, batch);
+  const int cols = cl.cols;
+  const uint32_t tiled_n = (uint32_t)cl.slots() * H;
   const int nb = stats_blocks(n);
   for (int b = 0; b < batch; ++b)
     for (int j = 0; j < P; ++j) {
@@ -451,7 +487,7 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
       hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
                          (double)n * (double)n, (double)n, sc + (size_t)b * P + j);
     }
-  const dim3 rows(p0->row_blocks, batch), tiles(p0->col_blocks, batch);
+  const dim3 rows(p0->row_blocks, batch), tiles(cl.blocks, batch);
   GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
   fa.ft = p0->ft;
   fa.field = field;
@@ -515,9 +551,9 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
       started = false;
       ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
       ca.sc = sc + j;
-      ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * p0->col_blocks : nullptr;
+      ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * cl.slots() : nullptr;
       if (is_step && backward) {
-        hipLaunchKernelGGL(ck.grad_col, tiles, dim3(ck.threads), ck.lds, stream, ca);
+        hipLaunchKernelGGL(cl.grad_col, tiles, dim3(cl.threads), cl.lds, stream, ca);
         plane_chirp(j, ga.q1y, ga.q1x);
         ga.first = j == 0;
         ga.last = j == P - 1;
@@ -532,12 +568,12 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
           hipLaunchKernelGGL(rk.grad_row, rows, dim3(rk.threads), rk.lds, stream, ga);
         }
       } else if (loss) {
-        hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
+        hipLaunchKernelGGL(cl.gs_col_nmse, tiles, dim3(cl.threads), cl.lds, stream, ca);
       }
     }
     if (loss && (k - chunk0 == kNmseChunk - 1 || k == states - 1)) {
       hipLaunchKernelGGL(k_loss_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
-                         (const float*)partials, p0->col_blocks, P, (const Scalars*)sc, loss + chunk0,
+                         (const float*)partials, cl.slots(), P, (const Scalars*)sc, loss + chunk0,
                          L.partial_stride, loss_stride);
       chunk0 = k + 1;
     }
@@ -649,8 +685,9 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   ra.tw = p->tw_row[0];
   ra.twr = p->tw_row[1];
 
-  const int cols = ck.cols;
-  const uint32_t tiled_n = (uint32_t)L.target_stride;
+  const ColLaunch cl = col_launch(p, window ? 1 : batch);
+  const int cols = cl.cols;
+  const uint32_t tiled_n = (uint32_t)cl.slots() * H;
   for (int b = 0; b < batch; ++b)
     hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, target_amp + (size_t)b * n,
                        w.target + (size_t)b * L.target_stride, H, W, cols, tiled_n, window);
@@ -678,10 +715,10 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   if (nmse || window)
     for (int b = 0; b < batch; ++b)
       enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream, window);
-  void (*col_hot)(GsColArgs) = window ? ck.gs_col_win : ck.gs_col;
-  void (*col_last)(GsColArgs) = window ? ck.gs_col_win_nmse : ck.gs_col_nmse;
+  void (*col_hot)(GsColArgs) = window ? ck.gs_col_win : cl.gs_col;
+  void (*col_last)(GsColArgs) = window ? ck.gs_col_win_nmse : cl.gs_col_nmse;
 
-  const dim3 rows(p->row_blocks, batch), tiles(p->col_blocks, batch);
+  const dim3 rows(p->row_blocks, batch), tiles(cl.blocks, batch);
   ra.phase0 = phase;
   ra.phase_out = iterations == 0 ? phase : nullptr;
   ra.levels_out = iterations == 0 ? levels : nullptr;
@@ -691,20 +728,20 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   for (int k = 0; k <= iterations; ++k) {
     const bool last = k == iterations;
     if (last && !nmse) break;
-    ca.partials = (nmse && !window) ? w.partials + (size_t)(k - chunk0) * p->col_blocks : nullptr;
-    ca.wpartials = (nmse && window) ? w.wpartials + (size_t)(k - chunk0) * 3 * p->col_blocks : nullptr;
+    ca.partials = (nmse && !window) ? w.partials + (size_t)(k - chunk0) * cl.slots() : nullptr;
+    ca.wpartials = (nmse && window) ? w.wpartials + (size_t)(k - chunk0) * 3 * cl.slots() : nullptr;
     if (last) {
-      hipLaunchKernelGGL(col_last, tiles, dim3(ck.threads), ck.lds, stream, ca);
+      hipLaunchKernelGGL(col_last, tiles, dim3(cl.threads), cl.lds, stream, ca);
     } else {
-      launch(p, HG_KERNEL_GS_REPLAY, stream, col_hot, tiles, ck.threads, ck.lds, ca);
+      launch(p, HG_KERNEL_GS_REPLAY, stream, col_hot, tiles, cl.threads, cl.lds, ca);
     }
     if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
       if (window)
         hipLaunchKernelGGL(k_window_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
-                           (const double*)w.wpartials, p->col_blocks, (const Scalars*)w.sc, n, nmse + chunk0);
+                           (const double*)w.wpartials, cl.slots(), (const Scalars*)w.sc, n, nmse + chunk0);
       else
         hipLaunchKernelGGL(k_nmse_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
-                           (const float*)w.partials, p->col_blocks, (const Scalars*)w.sc, nmse + chunk0,
+                           (const float*)w.partials, cl.slots(), (const Scalars*)w.sc, nmse + chunk0,
                            L.partial_stride, (size_t)iterations + 1);
       chunk0 = k + 1;
     }
@@ -863,6 +900,13 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   // order elsewhere.
   p->ft = p->row->row.ft != 0 && p->row->row.ft % p->col->col.cols == 0 ? p->row->row.ft : 0;
   const size_t n = (size_t)W * H;
+  {
+    const int cw = p->col->col_wide.cols;
+    p->wide_ok = cw > 0 && W % cw == 0 && (p->ft == 0 || p->ft % cw == 0);
+    p->col_blocks_wide = cw > 0 ? W / cw : 0;
+    p->col_slots = p->col_blocks * p->col->col.cols;
+    if (cw > 0) p->col_slots = std::max(p->col_slots, (W + cw - 1) / cw * cw);
+  }
   p->ws_bytes = ws_layout(p, 1).total;
   *out = p;
   return HG_OK;
@@ -1221,7 +1265,8 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
   const RowKernels& rk = p0->row->row;
   const ColKernels& ck = p0->col->col;
   const int cols = ck.cols;
-  const uint32_t tiled_n = (uint32_t)p0->col_blocks * cols * H;
+  const int slots = p0->col_blocks * cols;   // per-column error partials of one step
+  const uint32_t tiled_n = (uint32_t)slots * H;
   const int nb = stats_blocks(n);
   for (int j = 0; j < P; ++j) {
     const float* tj = target_amp + (size_t)j * n;
@@ -1273,14 +1318,14 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
   int chunk0 = 0;
   auto flush = [&](int upto) {   // reduce the partials of steps chunk0..upto
     hipLaunchKernelGGL(k_nmse_reduce_planes, dim3(upto - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
-                       (const float*)partials, p0->col_blocks, (const Scalars*)sc, P, chunk0, nmse + chunk0);
+                       (const float*)partials, slots, (const Scalars*)sc, P, chunk0, nmse + chunk0);
     chunk0 = upto + 1;
   };
   for (int s = 0; s < steps; ++s) {
     const int j = s % P;
     ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
     ca.sc = sc + j;
-    ca.partials = nmse ? partials + (size_t)(s - chunk0) * p0->col_blocks : nullptr;
+    ca.partials = nmse ? partials + (size_t)(s - chunk0) * slots : nullptr;
     hipLaunchKernelGGL(ck.gs_col, tiles, dim3(ck.threads), ck.lds, stream, ca);
     if (nmse && s - chunk0 == kNmseChunk - 1) flush(s);
     chirp_of(j, ra.q1y, ra.q1x);
@@ -1306,7 +1351,7 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
       hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, fa);
       ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
       ca.sc = sc + j;
-      ca.partials = partials + (size_t)(s - chunk0) * p0->col_blocks;
+      ca.partials = partials + (size_t)(s - chunk0) * slots;
       hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
       if (s - chunk0 == kNmseChunk - 1 || j == P - 1) flush(s);
     }

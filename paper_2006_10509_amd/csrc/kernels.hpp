@@ -352,14 +352,80 @@ struct RowLds {
   static constexpr int TAB = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
   static constexpr int WORDS = TAB + N;
 };
-template <int N>
-struct ColLds {
-  using C = ColCfg<N>;
+template <class CC>
+struct ColLdsOf {
+  using C = CC;
   using P = typename C::P;
   static_assert(tw_fits_reservation<P, C::THREADS>(), "one-order twiddles exceed the LDS reservation");
-  static constexpr int TWF = C::C * lds_len(N);
+  static constexpr int TWF = C::C * lds_len(P::N);
   static constexpr int WORDS = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
 };
+template <int N>
+using ColLds = ColLdsOf<ColCfg<N>>;
+
+// Column configuration of the single-hologram (WIDE = false) or batched
+// (WIDE = true) GS-family column passes.
+template <int N, bool WIDE>
+using ColCfgSel = std::conditional_t<WIDE, ColCfgWide<N>, ColCfg<N>>;
+
+// Per-column sums of a column pass in an order that does not depend on how
+// many columns share a workgroup, so that single and batched launches give
+// bitwise the same error values: a fixed pairwise tree over the team's
+// threads t within blocks of BT consecutive t (wavefront shuffles), then the
+// blocks added in order.  BT = 64 / (the widest column count of the length),
+// so that a block always lies inside one wavefront.
+template <int N>
+struct ColSum {
+  static constexpr int CMAX = ColCfgWide<N>::C > ColCfg<N>::C ? ColCfgWide<N>::C : ColCfg<N>::C;
+  static constexpr int T = ColCfg<N>::P::T;
+  static constexpr int BT = (64 / CMAX) < T ? (64 / CMAX) : T;
+  static constexpr int BLOCKS = T / BT;
+  static_assert(BT >= 1 && T % BT == 0, "column-sum blocks must tile the team");
+};
+
+// One float per thread of column c, team thread t -> the column's total in
+// the thread with t == 0 (others: unspecified).  red: C * BLOCKS floats.
+template <int N, class CC>
+__device__ __forceinline__ float column_sum(float v, int c, int t, float* red) {
+  using S = ColSum<N>;
+  static_assert(CC::C * S::BT <= 64, "a block must lie inside one wavefront");
+#pragma unroll
+  for (int off = CC::C; off < CC::C * S::BT; off <<= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (S::BLOCKS == 1) {
+    return v;
+  } else {
+    if (t % S::BT == 0) red[c * S::BLOCKS + t / S::BT] = v;
+    __syncthreads();
+    float s = 0.0f;
+    if (t == 0) {
+#pragma unroll
+      for (int b = 0; b < S::BLOCKS; ++b) s += red[c * S::BLOCKS + b];
+    }
+    return s;
+  }
+}
+
+// The same for doubles (signal-window sums).
+template <int N, class CC>
+__device__ __forceinline__ double column_sum_f64(double v, int c, int t, double* red) {
+  using S = ColSum<N>;
+  static_assert(CC::C * S::BT <= 64, "a block must lie inside one wavefront");
+#pragma unroll
+  for (int off = CC::C; off < CC::C * S::BT; off <<= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (S::BLOCKS == 1) {
+    return v;
+  } else {
+    if (t % S::BT == 0) red[c * S::BLOCKS + t / S::BT] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0) {
+#pragma unroll
+      for (int b = 0; b < S::BLOCKS; ++b) s += red[c * S::BLOCKS + b];
+    }
+    __syncthreads();
+    return s;
+  }
+}
 
 // Per-column table of a row pass (the Fresnel chirp q_x), read at the
 // positions of layout L.  With at most 16 register slots per thread, each
@@ -741,37 +807,6 @@ struct GsColArgs {
   }
 };
 
-// Wavefront then workgroup sums of three doubles per thread, fixed order;
-// the totals are valid in thread 0.
-template <int THREADS>
-__device__ __forceinline__ void block_sum3_f64(double& x, double& y, double& z, double* red) {
-  static_assert(THREADS % 64 == 0, "whole wavefronts");
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    x += __shfl_xor(x, off, 64);
-    y += __shfl_xor(y, off, 64);
-    z += __shfl_xor(z, off, 64);
-  }
-  constexpr int NW = THREADS / 64;
-  if constexpr (NW > 1) {
-    if ((threadIdx.x & 63) == 0) {
-      red[3 * (threadIdx.x >> 6) + 0] = x;
-      red[3 * (threadIdx.x >> 6) + 1] = y;
-      red[3 * (threadIdx.x >> 6) + 2] = z;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      x = y = z = 0.0;
-#pragma unroll
-      for (int i = 0; i < NW; ++i) {
-        x += red[3 * i + 0];
-        y += red[3 * i + 1];
-        z += red[3 * i + 2];
-      }
-    }
-  }
-}
-
 // Replay-plane pass of one state.  Column FFT -> R (the forward FFT2 of the
 // SLM field completes here); NMSE partial sum(d^2), d = a |R|^2 - b T^2; then
 //   COL_NMSE:    nothing more (last state of a call: no write-back);
@@ -785,20 +820,24 @@ __device__ __forceinline__ void block_sum3_f64(double& x, double& y, double& z, 
 // is not known in advance, so each workgroup writes three sums instead of one,
 // with x = a |R|^2 and y = b T^2 (b from the window's sum T^2):
 // sum x, sum x^2 and sum x y, in FP64 (k_window_nmse_reduce combines them).
+//
+// The error sums are per column (column_sum: an order independent of C), at
+// partials[column] (window: wpartials[j][column], j < 3), so that the single
+// (WIDE = false) and batched (WIDE = true) column configurations give bitwise
+// the same values.
 enum { COL_NMSE = 0, COL_REPLACE = 1, COL_GRAD = 2 };
-template <int N, int MODE, bool WIN = false>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
+template <int N, int MODE, bool WIN = false, bool WIDE = false>
+__global__ __launch_bounds__((ColCfgSel<N, WIDE>::THREADS)) void k_gs_col(GsColArgs a) {
   static_assert(!WIN || MODE != COL_GRAD, "no signal window in the gradient pass");
   a.select_item();
-  using C = ColCfg<N>;
+  using C = ColCfgSel<N, WIDE>;
   using P = typename C::P;
-  using LL = ColLds<N>;
+  using LL = ColLdsOf<C>;
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   using LB = Layout<P, true, true>;
   static_assert(LB::R == L0::R, "layout mismatch");
   constexpr bool BACK = MODE != COL_NMSE;
-  __shared__ float red[C::THREADS / 64];
   const int c = threadIdx.x % C::C, t = threadIdx.x / C::C;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int col = tile * C::C + c;
@@ -862,24 +901,28 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_gs_col(GsColArgs a) {
     tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
     if (live) for_layout<LB>(t, [&](int s, int y) { stg_field<N>(a.field, f.at(y), v[s]); });
   }
-  // The error's workgroup sum runs last, while the field stores drain: the
-  // replaced values do not depend on it, and its barrier and shuffles would
-  // otherwise sit between the two transforms.
+  // The error's column sums run last, while the field stores drain: the
+  // replaced values do not depend on them, and their barrier and shuffles
+  // would otherwise sit between the two transforms.
+  const uint32_t slot = (uint32_t)tile * C::C + c;   // the column's partial
   if constexpr (WIN) {
     if (nm) {
-      __shared__ double wred[3 * (C::THREADS / 64)];
+      __shared__ double wred[C::C * ColSum<N>::BLOCKS];
       if (!live) w1 = w2 = w3 = 0.0;
-      block_sum3_f64<C::THREADS>(w1, w2, w3, wred);
-      if (threadIdx.x == 0) {
-        const uint32_t nwg = gridDim.x;
-        a.wpartials[tile] = w1;
-        a.wpartials[nwg + tile] = w2;
-        a.wpartials[2 * nwg + tile] = w3;
+      w1 = column_sum_f64<N, C>(w1, c, t, wred);
+      w2 = column_sum_f64<N, C>(w2, c, t, wred);
+      w3 = column_sum_f64<N, C>(w3, c, t, wred);
+      if (t == 0) {
+        const uint32_t slots = gridDim.x * C::C;
+        a.wpartials[slot] = w1;
+        a.wpartials[slots + slot] = w2;
+        a.wpartials[2 * slots + slot] = w3;
       }
     }
   } else if (nm) {
-    const float s = block_sum<C::THREADS>(live ? acc : 0.0f, red);
-    if (threadIdx.x == 0) a.partials[tile] = s;
+    __shared__ float red[C::C * ColSum<N>::BLOCKS];
+    const float s = column_sum<N, C>(live ? acc : 0.0f, c, t, red);
+    if (t == 0) a.partials[slot] = s;
   }
 }
 
@@ -1339,6 +1382,14 @@ struct RowKernels {
   size_t lds;
   int ft;          // RowTeam<RowCfg<N>>::FT
 };
+// The GS-family column passes of the batched configuration (ColCfgWide).
+struct ColWideKernels {
+  void (*gs_col)(GsColArgs);
+  void (*gs_col_nmse)(GsColArgs);
+  void (*grad_col)(GsColArgs);
+  int cols, threads;     // cols = 0: the length has no batched configuration
+  size_t lds;
+};
 struct ColKernels {
   void (*prop_fwd)(PropColArgs);
   void (*prop_inv)(PropColArgs);
@@ -1358,6 +1409,7 @@ struct LengthEntry {
   int n;
   RowKernels row;
   ColKernels col;
+  ColWideKernels col_wide;
   // twiddle images (FP64 values) for the row / column launch shapes, in
   // forward and reversed radix order; sizes in complex entries
   int row_tw_len[2], col_tw_len[2];
@@ -1408,6 +1460,14 @@ LengthEntry make_length_entry() {
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
            k_gs_col<N, COL_REPLACE, true>, k_gs_col<N, COL_NMSE, true>, k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
            ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
+  if constexpr (ColCfgWide<N>::DEFINED) {
+    using CW = ColCfgWide<N>;
+    e.col_wide = {k_gs_col<N, COL_REPLACE, false, true>, k_gs_col<N, COL_NMSE, false, true>,
+                  k_gs_col<N, COL_GRAD, false, true>, CW::C, CW::THREADS,
+                  sizeof(float2) * ColLdsOf<CW>::WORDS};
+  } else {
+    e.col_wide = {nullptr, nullptr, nullptr, 0, 0, 0};
+  }
   using PR = typename RowCfg<N>::P;
   using PC = typename ColCfg<N>::P;
   e.row_tw_len[0] = TwRegs<PR, false>::TOTAL * PR::T;
