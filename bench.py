@@ -650,11 +650,18 @@ def main() -> int:
     alg_bytes = BYTES_PER_PX[dominant] * npx
     achieved = alg_bytes / (kstats[dominant] * 1e-3) / 1e9
     iter_gbs = sum(BYTES_PER_PX.values()) * npx * value / 1e9
+    per_kernel = {}
+    for name, ms in kstats.items():
+        gbs = BYTES_PER_PX[name] * npx / (ms * 1e-3) / 1e9
+        per_kernel[name] = {"us_per_launch": round(ms * 1e3, 3), "algorithmic_bytes_per_launch": BYTES_PER_PX[name] * npx,
+                            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                            "traffic": measured_traffic(name)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
                 "kernel": dominant, "us_per_launch": round(kstats[dominant] * 1e3, 3),
                 "timing": f"HIP events around groups of {TIMING_REPEATS} back-to-back launches",
                 "algorithmic_bytes_per_launch": alg_bytes,
+                "kernels": per_kernel,
                 "iteration_gbs": round(iter_gbs, 1), "iteration_frac": round(iter_gbs / HBM_PEAK_GBS, 4)}
 
     ttn = gb = None
