@@ -32,6 +32,8 @@ step by step in the order the method performs it:
                   (the paper's HoloGenAlgDSCuda / HoloGenAlgSACuda, Sec. 7.3).
   window.py       GS with a signal window (region of interest) in the replay
                   plane (Fienup 1982; Wyrowski & Bryngdahl 1988).
+  amplitude.py    GS for an amplitude-only SLM (non-negativity constraint,
+                  Fienup 1982).
 
 Where the paper is silent, each module's docstring states the reading it
 takes.  Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
@@ -48,6 +50,7 @@ from .ospr import ospr, ospr_pairs
 from .grad import source_chirp, loss_and_gradient, adam_update, grad_descent
 from .search import pixel_search
 from .window import gs_window, window_nmse
+from .amplitude import gs_amplitude, nonnegative_real
 
 __all__ = [
     "dft_naive", "fft", "ifft", "fft2", "ifft2", "fftshift", "ifftshift",
@@ -56,5 +59,5 @@ __all__ = [
     "quantise_level", "quantise_phase_level", "phase_only", "replace_amplitude",
     "binarise", "nmse", "gs_iterate", "gs_multiplane", "ospr", "ospr_pairs",
     "source_chirp", "loss_and_gradient", "adam_update", "grad_descent", "pixel_search",
-    "gs_window", "window_nmse",
+    "gs_window", "window_nmse", "gs_amplitude", "nonnegative_real",
 ]
