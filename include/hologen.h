@@ -56,7 +56,8 @@ typedef enum {
 } hg_status;
 
 enum { HG_FOURIER = 0, HG_FRESNEL = 1, HG_ANGULAR = 2 };                               /* propagation */
-enum { HG_PHASE = 0, HG_PHASE_QUANTISED = 1, HG_BINARY_PHASE = 2 };   /* SLM modulation */
+enum { HG_PHASE = 0, HG_PHASE_QUANTISED = 1, HG_BINARY_PHASE = 2,
+       HG_AMPLITUDE = 3 };                                        /* SLM modulation */
 enum { HG_FORWARD = 1 /* SLM -> replay */, HG_INVERSE = -1 /* replay -> SLM */ };
 
 typedef struct {
@@ -73,9 +74,12 @@ typedef struct {
                               that no sampled plane wave is evanescent          */
   double distance;         /* metres; Fresnel: finite and > 0; angular: finite
                               (negative propagates backwards)                   */
-  int32_t modulation;      /* HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE    */
-  int32_t levels;          /* 0 for HG_PHASE; 2..256 for HG_PHASE_QUANTISED;
-                              2 for HG_BINARY_PHASE                              */
+  int32_t modulation;      /* HG_PHASE, HG_PHASE_QUANTISED, HG_BINARY_PHASE or
+                              HG_AMPLITUDE (continuous amplitude-only SLM: the
+                              SLM-plane constraint is the nearest non-negative
+                              real value, see hg_gs_iterate)                    */
+  int32_t levels;          /* 0 for HG_PHASE and HG_AMPLITUDE; 2..256 for
+                              HG_PHASE_QUANTISED; 2 for HG_BINARY_PHASE          */
 } hg_plan_desc;
 
 /* Create a plan on the current HIP device: validates the descriptor, builds
@@ -140,7 +144,18 @@ hg_status hg_propagate(hg_plan plan, const void* in_c64, void* out_c64, int32_t 
  *              NULL to skip.
  * nmse         [iterations + 1] float; NULL to skip the error metric.
  * iterations   >= 0.
- * workspace    hg_workspace_bytes(plan) bytes of device memory.  (required) */
+ * workspace    hg_workspace_bytes(plan) bytes of device memory.  (required)
+ *
+ * HG_AMPLITUDE plans (HG_FOURIER or HG_FRESNEL; no illumination): an
+ * amplitude-only SLM, whose SLM types the paper names without defining them
+ * (Sec. 3.2, SLMTypeOption, MultiAmpSLM).  Read here as the continuous
+ * amplitude modulator under uniform illumination: H = a with a real a >= 0,
+ * and P(G) = max(Re G, 0), the nearest such value (Fienup 1982).  `phase`
+ * then holds the SLM amplitude instead of a phase: in = starting amplitude
+ * a_0 (finite; negative values constrain to 0), out = a_n of the last state
+ * at the scale of the normalised inverse transform (a_0 itself when
+ * iterations = 0); levels receives 0.  The field energy changes between
+ * states, so sum I is summed rather than taken from Parseval. */
 hg_status hg_gs_iterate(hg_plan plan, const float* target_amp, const float* illumination, float* phase,
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
                         hipStream_t stream);

@@ -298,8 +298,12 @@ hg_status validate_desc(const hg_plan_desc* d) {
     case HG_BINARY_PHASE:
       if (d->levels != 2) return fail(HG_ERR_INVALID_ARGUMENT, "levels must be 2 for HG_BINARY_PHASE");
       break;
+    case HG_AMPLITUDE:
+      if (d->levels != 0) return fail(HG_ERR_INVALID_ARGUMENT, "levels must be 0 for HG_AMPLITUDE");
+      break;
     default:
-      return fail(HG_ERR_INVALID_ARGUMENT, "modulation must be HG_PHASE, HG_PHASE_QUANTISED or HG_BINARY_PHASE");
+      return fail(HG_ERR_INVALID_ARGUMENT,
+                  "modulation must be HG_PHASE, HG_PHASE_QUANTISED, HG_BINARY_PHASE or HG_AMPLITUDE");
   }
   return HG_OK;
 }
@@ -380,7 +384,7 @@ int stats_blocks(size_t n) {
 }
 
 void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const float* illum, double intensity_sum,
-                   Scalars* out, hipStream_t s, const uint8_t* window = nullptr) {
+                   Scalars* out, hipStream_t s, const uint8_t* window = nullptr, int unit_target_scale = 0) {
   const size_t n = npix(p);
   const int nb = stats_blocks(n);
   // sum I of a GS state: N_px sum A^2 after the unnormalised FFT2; the
@@ -388,7 +392,7 @@ void enqueue_stats(hg_plan p, const Workspace& w, const float* target, const flo
   const double a2_scale = p->desc.propagation == HG_ANGULAR ? (double)n * (double)n : (double)n;
   hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, s, target, illum, n, w.stats, window);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, s, (const double*)w.stats, nb, n, illum ? 1 : 0,
-                     intensity_sum, a2_scale, out);
+                     intensity_sum, a2_scale, out, unit_target_scale);
 }
 
 // Column-pass configuration of a GS-family launch over `batch` holograms or
@@ -684,8 +688,15 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
                                : make_float2(1.0f, 0.0f);
   ra.tw = p->tw_row[0];
   ra.twr = p->tw_row[1];
+  // amplitude-only SLM: its field energy changes between states, so the
+  // error comes from the exact three-sum column pass (the windowed one, with
+  // every pixel inside and the target imposed as given)
+  const bool amplitude = p->desc.modulation == HG_AMPLITUDE;
+  ra.slm.amplitude = amplitude ? 1 : 0;
+  ra.slm.amp_scale = (float)(1.0 / (double)n);
+  const bool exact = window != nullptr || amplitude;
 
-  const ColLaunch cl = col_launch(p, window ? 1 : batch);
+  const ColLaunch cl = col_launch(p, exact ? 1 : batch);
   const int cols = cl.cols;
   const uint32_t tiled_n = (uint32_t)cl.slots() * H;
   for (int b = 0; b < batch; ++b)
@@ -706,17 +717,18 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   ca.sc_stride = 1;
   ca.partial_stride = (uint32_t)L.partial_stride;
 
-  const int mode = p->levels == 0 ? GS_CONT
+  const int mode = amplitude ? GS_AMP : p->levels == 0 ? GS_CONT
                  : (p->levels == 2 || p->levels == 4 || p->levels == 8) ? p->levels : GS_QATAN;
   // steady-state kernel unless the pass needs illumination or produces outputs
   void (*gs_row_hot)(GsRowArgs) = rk.gs_row[gs_mode_index(mode)][p->desc.propagation == HG_FRESNEL ? 1 : 0];
 
   // a window needs its target scale even without the error trace
-  if (nmse || window)
+  if (nmse || exact)
     for (int b = 0; b < batch; ++b)
-      enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream, window);
-  void (*col_hot)(GsColArgs) = window ? ck.gs_col_win : cl.gs_col;
-  void (*col_last)(GsColArgs) = window ? ck.gs_col_win_nmse : cl.gs_col_nmse;
+      enqueue_stats(p, w, target_amp + (size_t)b * n, illumination, 0.0, w.sc + b, stream, window,
+                    amplitude ? 1 : 0);
+  void (*col_hot)(GsColArgs) = exact ? ck.gs_col_win : cl.gs_col;
+  void (*col_last)(GsColArgs) = exact ? ck.gs_col_win_nmse : cl.gs_col_nmse;
 
   const dim3 rows(p->row_blocks, batch), tiles(cl.blocks, batch);
   ra.phase0 = phase;
@@ -728,15 +740,15 @@ hg_status gs_run(hg_plan p, int batch, const float* target_amp, const float* ill
   for (int k = 0; k <= iterations; ++k) {
     const bool last = k == iterations;
     if (last && !nmse) break;
-    ca.partials = (nmse && !window) ? w.partials + (size_t)(k - chunk0) * cl.slots() : nullptr;
-    ca.wpartials = (nmse && window) ? w.wpartials + (size_t)(k - chunk0) * 3 * cl.slots() : nullptr;
+    ca.partials = (nmse && !exact) ? w.partials + (size_t)(k - chunk0) * cl.slots() : nullptr;
+    ca.wpartials = (nmse && exact) ? w.wpartials + (size_t)(k - chunk0) * 3 * cl.slots() : nullptr;
     if (last) {
       hipLaunchKernelGGL(col_last, tiles, dim3(cl.threads), cl.lds, stream, ca);
     } else {
       launch(p, HG_KERNEL_GS_REPLAY, stream, col_hot, tiles, cl.threads, cl.lds, ca);
     }
     if (nmse && (k - chunk0 == kNmseChunk - 1 || last)) {
-      if (window)
+      if (exact)
         hipLaunchKernelGGL(k_window_nmse_reduce, dim3(k - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
                            (const double*)w.wpartials, cl.slots(), (const Scalars*)w.sc, n, nmse + chunk0);
       else
@@ -980,6 +992,11 @@ hg_status hg_gs_iterate(hg_plan p, const float* target_amp, const float* illumin
                         uint8_t* levels, float* nmse, int32_t iterations, void* workspace, hipStream_t stream) {
   const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
   if (st != HG_OK) return st;
+  if (p->desc.modulation == HG_AMPLITUDE) {
+    if (illumination) return fail(HG_ERR_INVALID_ARGUMENT, "an HG_AMPLITUDE plan takes no illumination");
+    if (p->desc.propagation == HG_ANGULAR)
+      return fail(HG_ERR_INVALID_ARGUMENT, "HG_AMPLITUDE needs an HG_FOURIER or HG_FRESNEL plan");
+  }
   if (p->desc.propagation == HG_ANGULAR)
     return gs_run_angular(p, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
   return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
@@ -991,6 +1008,8 @@ hg_status hg_gs_iterate_window(hg_plan p, const float* target_amp, const uint8_t
   const hg_status st = gs_validate(p, target_amp, phase, iterations, workspace);
   if (st != HG_OK) return st;
   if (!window) return fail(HG_ERR_INVALID_ARGUMENT, "window is NULL");
+  if (p->desc.modulation == HG_AMPLITUDE)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_window takes phase-only plans");
   if (p->desc.propagation == HG_ANGULAR)
     return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_window takes HG_FOURIER or HG_FRESNEL plans");
   return gs_run(p, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream, window);
@@ -1025,6 +1044,8 @@ hg_status hg_gs_iterate_batched(hg_plan p, int32_t batch, const float* target_am
   if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
   if (p->desc.propagation == HG_ANGULAR)
     return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_batched takes HG_FOURIER or HG_FRESNEL plans");
+  if (p->desc.modulation == HG_AMPLITUDE)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_iterate_batched takes phase-only plans");
   if ((size_t)batch * field_elems(p) > (size_t)UINT32_MAX)
     return fail(HG_ERR_INVALID_ARGUMENT, "batch * height * (width rounded up to a multiple of 4) must be below 2^32");
   return gs_run(p, batch, target_amp, illumination, phase, levels, nmse, iterations, workspace, stream);
@@ -1252,6 +1273,8 @@ hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float*
   for (int j = 1; j < n_planes; ++j)
     if (planes[j]->desc.modulation != planes[0]->desc.modulation || planes[j]->levels != planes[0]->levels)
       return fail(HG_ERR_INVALID_ARGUMENT, "all planes must have the same modulation and levels");
+  if (planes[0]->desc.modulation == HG_AMPLITUDE)
+    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_multiplane takes phase-only plans");
   const int P = n_planes;
   hg_plan p0 = planes[0];
   const int W = p0->desc.width, H = p0->desc.height;

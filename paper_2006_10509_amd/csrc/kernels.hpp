@@ -65,6 +65,9 @@ struct SlmConstraint {
   float inv_delta;                     // L / (2 pi)
   double inv_delta_f64;                // L / (2 pi) for the one-off quantisation of phi0
   float2 half_step;                    // exp(i pi / L): rotates decision boundaries onto axes
+  int amplitude;                       // amplitude-only SLM: nearest non-negative real value
+  float amp_scale;                     // amplitude output of a loop state: 1 / (H W) undoes
+                                       // the two unscaled inverse transforms
 };
 
 // ---------------------------------------------------------------------------
@@ -585,13 +588,18 @@ struct GsRowArgs {
 };
 
 // SLM-constraint variants of the steady-state row pass.
-enum { GS_CONT = 0, GS_QATAN = 1, GS_Q2 = 2, GS_Q4 = 4, GS_Q8 = 8 };
+enum { GS_CONT = 0, GS_QATAN = 1, GS_Q2 = 2, GS_Q4 = 4, GS_Q8 = 8, GS_AMP = 16 };
 __host__ __device__ constexpr int gs_mode_index(int mode) {
-  return mode == GS_CONT ? 0 : mode == GS_QATAN ? 1 : mode == GS_Q2 ? 2 : mode == GS_Q4 ? 3 : 4;
+  return mode == GS_CONT ? 0 : mode == GS_QATAN ? 1 : mode == GS_Q2 ? 2 : mode == GS_Q4 ? 3 : mode == GS_Q8 ? 4 : 5;
 }
 
-__device__ __forceinline__ void write_state(const GsRowArgs& a, uint32_t idx, float2 u, int level) {
-  if (a.slm.lvl_tab) {
+// Output of one SLM state: phase and level (phase-only SLMs) or the amplitude
+// u.x scaled by amp (amplitude-only SLMs; level 0).
+__device__ __forceinline__ void write_state(const GsRowArgs& a, uint32_t idx, float2 u, int level, float amp = 1.0f) {
+  if (a.slm.amplitude) {
+    if (a.phase_out) stg(a.phase_out, idx, u.x * amp);
+    if (a.levels_out) stg(a.levels_out, idx, (uint8_t)0);
+  } else if (a.slm.lvl_tab) {
     if (a.phase_out) stg(a.phase_out, idx, (float)level * (TWO_PI_F / (float)a.slm.levels));
     if (a.levels_out) stg(a.levels_out, idx, (uint8_t)level);
   } else {
@@ -629,7 +637,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row_start(GsRowArgs a
   for_layout<L0>(t, [&](int s, int x) {
     float2 u;
     int level = 0;
-    if (a.slm.lvl_tab) {
+    if (a.slm.amplitude) {
+      u = make_float2(fmaxf(ph[s], 0.0f), 0.0f);   // the starting amplitude, constrained
+    } else if (a.slm.lvl_tab) {
       level = quant_phase(ph[s], a.slm.levels, a.slm.inv_delta_f64);
       u = a.slm.lvl_tab[level];
     } else {
@@ -661,6 +671,10 @@ __device__ __forceinline__ float2 slm_constrain(float2 g, const SlmConstraint& s
   if constexpr (MODE == GS_CONT) {
     level = 0;
     return unit_of(g);
+  } else if constexpr (MODE == GS_AMP) {
+    // amplitude-only SLM: the nearest non-negative real value
+    level = 0;
+    return make_float2(fmaxf(g.x, 0.0f), 0.0f);
   } else if constexpr (MODE == GS_QATAN) {
     level = quant_level(g, slm);
     return slm.lvl_tab[level];
@@ -677,6 +691,7 @@ __device__ __forceinline__ float2 slm_constrain(float2 g, const SlmConstraint& s
 
 // Runtime-selected constraint for the general row pass.
 __device__ __forceinline__ float2 slm_constrain_rt(float2 g, const SlmConstraint& slm, int& level) {
+  if (slm.amplitude) return slm_constrain<GS_AMP>(g, slm, level);
   if (!slm.lvl_tab) return slm_constrain<GS_CONT>(g, slm, level);
   if (slm.levels == 8) return slm_constrain<GS_Q8>(g, slm, level);
   if (slm.levels == 4) return slm_constrain<GS_Q4>(g, slm, level);
@@ -772,7 +787,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
       }
       int level;
       float2 u = slm_constrain_rt(g, a.slm, level);
-      if (out) write_state(a, row + x, u, level);
+      if (out) write_state(a, row + x, u, level, a.slm.amp_scale);
       if (a.illum) u = cscale(u, ill[s]);
       if (a.q_out_set && fres_out) q = cmul(qoy, qo.at(s, x));
       v[s] = fres_out ? cmul(u, q) : u;
@@ -1368,7 +1383,7 @@ struct RowKernels {
   void (*prop_fwd)(PropRowArgs);
   void (*prop_inv)(PropRowArgs);
   void (*gs_start)(GsRowArgs);
-  void (*gs_row[5][2])(GsRowArgs);   // steady state [gs_mode_index][Fresnel]
+  void (*gs_row[6][2])(GsRowArgs);   // steady state [gs_mode_index][Fresnel]
   void (*gs_row_general)(GsRowArgs); // outputs / illumination / any mode
   void (*gs_row_mp[5])(GsRowArgs);   // multi-plane steady state [gs_mode_index]
   void (*ospr_a)(OsprRowArgs);
@@ -1430,6 +1445,8 @@ LengthEntry make_length_entry() {
   e.row.prop_fwd = k_prop_row<N, -1>;
   e.row.prop_inv = k_prop_row<N, +1>;
   e.row.gs_start = k_gs_row_start<N>;
+  e.row.gs_row[5][0] = k_gs_row<N, GS_AMP, false>;
+  e.row.gs_row[5][1] = k_gs_row<N, GS_AMP, true>;
   e.row.gs_row[0][0] = k_gs_row<N, GS_CONT, false>;
   e.row.gs_row[0][1] = k_gs_row<N, GS_CONT, true>;
   e.row.gs_row[1][0] = k_gs_row<N, GS_QATAN, false>;

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_partial(const float* __
 // intensity_sum (N_px^2 for an OSPR average of +-1 holograms).
 __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __restrict__ part, int nblk, size_t n,
                                                                int has_illum, double intensity_sum, double a2_scale,
-                                                               Scalars* __restrict__ sc) {
+                                                               Scalars* __restrict__ sc, int unit_target_scale = 0) {
   __shared__ double red[STATS_THREADS];
   double t2 = 0.0, t4 = 0.0, a2 = 0.0;
   for (int i = threadIdx.x; i < nblk; i += STATS_THREADS) {
@@ -113,7 +113,9 @@ __global__ __launch_bounds__(STATS_THREADS) void k_stats_final(const double* __r
     sc->b = (float)(npx / t2);
     sc->denom = npx * npx * t4 / (t2 * t2);
     sc->g = (float)(2.0 * (npx / s_i) / sc->denom);
-    sc->c = (float)sqrt(s_i / t2);
+    // the target scale of a signal window; 1 where the target is imposed as
+    // given (an amplitude-only SLM, whose field energy is not fixed)
+    sc->c = unit_target_scale ? 1.0f : (float)sqrt(s_i / t2);
   }
 }
 

@@ -26,6 +26,7 @@ HG_ANGULAR = 2
 HG_PHASE = 0
 HG_PHASE_QUANTISED = 1
 HG_BINARY_PHASE = 2
+HG_AMPLITUDE = 3
 HG_FORWARD = 1
 HG_INVERSE = -1
 

@@ -59,6 +59,7 @@ def create(**kw):
     (dict(modulation=1, levels=257), hg.HG_ERR_INVALID_ARGUMENT),
     (dict(modulation=2, levels=4), hg.HG_ERR_INVALID_ARGUMENT),
     (dict(modulation=9), hg.HG_ERR_INVALID_ARGUMENT),
+    (dict(modulation=3, levels=4), hg.HG_ERR_INVALID_ARGUMENT),     # amplitude-only: continuous
 ])
 def test_plan_create_rejects_bad_descriptors(kw, status):
     st, handle = create(**kw)
