@@ -198,6 +198,8 @@ def test_gs_fresnel_1024_L8_first_10_iterations():
     (2160, 3840, 0, False, 2),
     (8192, 16, 8, True, 3),
     (16, 8192, 4, False, 3),
+    # 4096-point rows on the tiles of 4
+    (1024, 4096, 4, False, 2),
 ])
 def test_gs_shapes_and_modes(h, w, levels, fresnel, iters):
     print(f"gs {h}x{w} L={levels} fresnel={fresnel} it={iters}", flush=True)
