@@ -244,6 +244,12 @@ template <int MUL>
 struct LdsView {
   float2* base;
   __device__ __forceinline__ float2& at(int i) const { return base[lds_pad(i) * MUL]; }
+  // Distance in float2 elements between at(i) and at(i + d) when d is a
+  // multiple of the padding period, or when i and i + d lie in one padding
+  // block: then it does not depend on i.
+  __host__ __device__ static constexpr int padded_span(int d) {
+    return (d % (1 << PAD_LOG) == 0 ? d + (d >> PAD_LOG) : d) * MUL;
+  }
 };
 
 // Synchronisation between exchange phases.  A team inside one wavefront only
@@ -377,23 +383,56 @@ __device__ __forceinline__ void stage_exchange(float2* v, int t, LdsView<MUL> ld
   constexpr int R2 = P::radix(S_ + 1, REV);
   constexpr int NR2 = P::N / R2;
   constexpr int ROUNDS2 = P::rounds(S_ + 1, REV);
+  // Where the padded distance between two slots does not depend on the
+  // thread (strides that are multiples of the padding period, or a run of R
+  // inside one padding block), the slots are addressed from one base pointer
+  // with constant offsets instead of one padded index each.
+  constexpr int PERIOD = 1 << PAD_LOG;
+  constexpr bool W_SLOTS = NS % PERIOD == 0 || (NS == 1 && PERIOD % R == 0);
+  constexpr bool W_ROUNDS = W_SLOTS && P::T % NS == 0 && (P::T * R) % PERIOD == 0;
+  constexpr bool R_SLOTS = NR2 % PERIOD == 0;
+  constexpr bool R_ROUNDS = R_SLOTS && P::T % PERIOD == 0;
+  using LV = LdsView<MUL>;
+  float2* const w0 = W_ROUNDS ? &lds.at((t - t % NS) * R + t % NS) : nullptr;
 #pragma unroll
   for (int m = 0; m < ROUNDS; ++m) {
     const int j = t + m * P::T;
     if (P::full(S_, REV) || j < NR) {
-      const int k = j % NS;
-      const int base = (j - k) * R + k;
+      if constexpr (W_ROUNDS) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds.at(base + r * NS) = v[m * R + r];
+        for (int r = 0; r < R; ++r)
+          w0[LV::padded_span(m * P::T * R) + LV::padded_span(r * NS)] = v[m * R + r];
+      } else {
+        const int k = j % NS;
+        const int base = (j - k) * R + k;
+        if constexpr (W_SLOTS) {
+          float2* p = &lds.at(base);
+#pragma unroll
+          for (int r = 0; r < R; ++r) p[LV::padded_span(r * NS)] = v[m * R + r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds.at(base + r * NS) = v[m * R + r];
+        }
+      }
     }
   }
   team_sync<WAVE_SYNC>();
+  const float2* const r0 = R_ROUNDS ? &lds.at(t) : nullptr;
 #pragma unroll
   for (int m = 0; m < ROUNDS2; ++m) {
     const int j = t + m * P::T;
     if (P::full(S_ + 1, REV) || j < NR2) {
+      if constexpr (R_ROUNDS) {
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[m * R2 + r] = lds.at(j + r * NR2);
+        for (int r = 0; r < R2; ++r) v[m * R2 + r] = r0[LV::padded_span(m * P::T + r * NR2)];
+      } else if constexpr (R_SLOTS) {
+        const float2* p = &lds.at(j);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[m * R2 + r] = p[LV::padded_span(r * NR2)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[m * R2 + r] = lds.at(j + r * NR2);
+      }
     }
   }
   team_sync<WAVE_SYNC>();
