@@ -465,9 +465,21 @@ template <class P, bool REV>
 using TwLdsFor = TwLds<P, P::PALINDROME ? false : REV>;
 
 // Twiddle registers worth holding for a whole transform: up to 16 complex
-// values (32 VGPRs).  Larger sets stay in LDS and are read at each use, since
-// holding them would push the transform's registers into AGPR spills.
+// values (32 VGPRs), or more while twiddles and data together take at most 32
+// complex values (64 VGPRs; e.g. 22 twiddles beside 8 data values).  Larger
+// sets stay in LDS and are read at each use, since holding them would push
+// the transform's registers into AGPR spills.
 constexpr int TW_REG_MAX = 16;
+constexpr int TW_DATA_REG_MAX = 32;
+
+// Whether the kernels of plan P that run both transform orders hold their
+// twiddles in registers (PassTwiddles with DATA_REGS), so that no LDS is
+// reserved for twiddle images at this length.
+template <class P>
+constexpr bool tw_both_in_regs() {
+  constexpr int f = TwRegs<P, false>::TOTAL, r = TwRegs<P, true>::TOTAL;
+  return (f <= TW_REG_MAX && r <= TW_REG_MAX) || f + (P::PALINDROME ? 0 : r) + P::REGS <= TW_DATA_REG_MAX;
+}
 
 // Full transform of order REV with twiddles from the workgroup's LDS image:
 // copied into registers once when the set is small, else read where used.
@@ -518,28 +530,33 @@ constexpr int TW_LDS_MAX_WORDS = 8704;
 
 // Twiddles of one pass kernel for the transform orders it runs (USE_F: the
 // forward radix order, USE_R: the reversed one).  When every set it needs
-// holds at most TW_REG_MAX values per thread, each thread loads its own
+// fits in registers (tw_in_regs), each thread loads its own
 // entries from the global twiddle image straight into registers: coalesced
 // loads that go out with the kernel's data loads and need neither LDS nor a
 // barrier.  Larger sets are copied into the workgroup's LDS at `lds_img`
 // (visible after the caller's barrier) and read from there, unless they
 // exceed TW_LDS_MAX_WORDS: those are read from the global image itself.
-template <class P, int THREADS, bool USE_F, bool USE_R>
+template <class P, int THREADS, bool USE_F, bool USE_R, bool DATA_REGS = true>
 struct PassTwiddles {
   static constexpr bool PAL = P::PALINDROME;
   static constexpr bool NEED_F = USE_F || (USE_R && PAL);  // a palindrome runs both orders on the forward set
   static constexpr bool NEED_R = USE_R && !PAL;
   static constexpr int LEN_F = TwRegs<P, false>::TOTAL * P::T;
   static constexpr int LEN_R = TwRegs<P, true>::TOTAL * P::T;
-  static constexpr bool IN_REGS = (!NEED_F || TwRegs<P, false>::TOTAL <= TW_REG_MAX) &&
-                                  (!NEED_R || TwRegs<P, true>::TOTAL <= TW_REG_MAX);
+  // every set needed within TW_REG_MAX, or (DATA_REGS: kernels whose other
+  // registers leave room) all of them with the data within TW_DATA_REG_MAX
+  static constexpr int REG_WORDS = (NEED_F ? TwRegs<P, false>::TOTAL : 0) + (NEED_R ? TwRegs<P, true>::TOTAL : 0);
+  static constexpr bool IN_REGS = ((!NEED_F || TwRegs<P, false>::TOTAL <= TW_REG_MAX) &&
+                                   (!NEED_R || TwRegs<P, true>::TOTAL <= TW_REG_MAX)) ||
+                                  (DATA_REGS && REG_WORDS + P::REGS <= TW_DATA_REG_MAX);
   static constexpr int IMAGE_WORDS = (NEED_F ? LEN_F : 0) + (NEED_R ? LEN_R : 0);
   // Both orders' images: the LDS a launch of this length reserves is sized by
   // the kernels that run both orders, so a kernel running one order must take
   // the global path whenever those do.
   static constexpr int FULL_WORDS = LEN_F + (PAL ? 0 : LEN_R);
-  // read at the point of use from the global image
-  static constexpr bool IN_GLOBAL = !IN_REGS && FULL_WORDS > TW_LDS_MAX_WORDS;
+  // read at the point of use from the global image (also where the length's
+  // other kernels hold their twiddles in registers and reserve no LDS)
+  static constexpr bool IN_GLOBAL = !IN_REGS && (FULL_WORDS > TW_LDS_MAX_WORDS || tw_both_in_regs<P>());
   // true when begin() writes LDS and the caller must barrier before run()
   static constexpr bool USES_LDS = !IN_REGS && !IN_GLOBAL;
   // LDS words the twiddles take (0 in register and global modes)

@@ -245,10 +245,12 @@ template <class C>
 struct RowTeam {
   using P = typename C::P;
   // Tile width of the tiled layout these row kernels take (0: none).  The
-  // teams must interleave (s_barrier exchanges, several rows) and every
-  // register slot must lie a multiple of FT from t.
+  // teams must interleave (s_barrier exchanges) and every register slot must
+  // lie a multiple of FT from t.  With one team (one row) per workgroup a
+  // wavefront access covers FT-wide pieces of many tiles, whose lines the
+  // workgroups of the neighbouring rows (on the same XCD) complete in L2.
   static constexpr int FT = C::FT;
-  static_assert(FT == 0 || (!C::WAVE_SYNC && C::TEAMS > 1 && (FT & (FT - 1)) == 0 && P::T % FT == 0 &&
+  static_assert(FT == 0 || (!C::WAVE_SYNC && (FT & (FT - 1)) == 0 && P::T % FT == 0 &&
                             Layout<P, true, false>::STRIDE % FT == 0 && Layout<P, false, true>::STRIDE % FT == 0 &&
                             Layout<P, false, false>::STRIDE % FT == 0),
                 "tile width unusable with this row shape");
@@ -353,7 +355,10 @@ struct RowLds {
   static constexpr int TEAM = lds_len(N) + (20 - lds_len(N) % 16) % 16;
   static constexpr int TWF = C::TEAMS * TEAM;
   static constexpr int TAB = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
-  static constexpr int WORDS = TAB + N;
+  // a per-column table is shared through LDS only when a thread's share of it
+  // would take more than 16 registers (RowTable)
+  static constexpr bool TABLE_IN_LDS = P::REGS > 16;
+  static constexpr int WORDS = TAB + (TABLE_IN_LDS ? N : 0);
 };
 template <class CC>
 struct ColLdsOf {
@@ -438,7 +443,7 @@ __device__ __forceinline__ double column_sum_f64(double v, int c, int t, double*
 template <int N, class L>
 struct RowTable {
   using P = typename RowCfg<N>::P;
-  static constexpr bool IN_REGS = P::REGS <= 16;
+  static constexpr bool IN_REGS = !RowLds<N>::TABLE_IN_LDS;
   static constexpr bool USES_LDS = !IN_REGS;
   float2 r[IN_REGS ? P::REGS : 1];
   __device__ __forceinline__ void begin(const float2* src, int t) {
@@ -499,13 +504,24 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_prop_row(PropRowArgs a) 
   const uint32_t row = (uint32_t)rt.y * N;
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.in, row + wrap_add<N>(x, a.sx_in)); });
   issue_loads_here();
-  PassTwiddles<P, C::THREADS, true, false> tw;
+  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
-  if (a.pre_y) lds_fill<C::THREADS, N>(hg_dyn_lds + LL::TAB, a.pre_x);
-  __syncthreads();
+  // the pre-multiply table: each thread's entries in registers, or shared
+  // through LDS when they would take more than 16 registers
+  float2 pre[LL::TABLE_IN_LDS ? 1 : P::REGS];
+  if constexpr (LL::TABLE_IN_LDS) {
+    if (a.pre_y) lds_fill<C::THREADS, N>(hg_dyn_lds + LL::TAB, a.pre_x);
+  } else {
+    if (a.pre_y) for_layout<L0>(t, [&](int s, int x) { pre[s] = a.pre_x[wrap_add<N>(x, a.sx_in)]; });
+  }
+  if constexpr (LL::TABLE_IN_LDS || TW::USES_LDS) __syncthreads();
   if (a.pre_y) {
     const float2 py = a.pre_y[rt.y];
-    for_layout<L0>(t, [&](int s, int x) { v[s] = cmul(v[s], cmul(py, hg_dyn_lds[LL::TAB + wrap_add<N>(x, a.sx_in)])); });
+    for_layout<L0>(t, [&](int s, int x) {
+      const float2 q = LL::TABLE_IN_LDS ? hg_dyn_lds[LL::TAB + wrap_add<N>(x, a.sx_in)] : pre[LL::TABLE_IN_LDS ? 0 : s];
+      v[s] = cmul(v[s], cmul(py, q));
+    });
   }
   tw.template run<false, DIR, C::WAVE_SYNC>(v, t, lds);
   if (rt.live) for_layout<L1>(t, [&](int s, int k) { stg(a.out, row + wrap_add<N>(k, a.sx_out), v[s]); });
@@ -735,7 +751,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
     if (a.illum) for_layout<LF>(t, [&](int s, int x) { ill[s] = ldg(a.illum, row + x); });
   }
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, true, true>;
+  // the general and multi-plane passes hold more registers: twiddles in
+  // registers only where they are few
+  using TW = PassTwiddles<P, C::THREADS, true, true, !GENERAL && !MP>;
   using QX = RowTable<N, LF>;
   using QO = RowTableDirect<N, LF>;
   TW tw;
@@ -1012,7 +1030,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
     vv[s] = adam ? ldg_f<N>(a.v, row + x) : 0.0f;
   });
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, NEXT, true>;
+  using TW = PassTwiddles<P, C::THREADS, NEXT, true, !NEXT>;
   using QX = RowTable<N, LF>;
   using QN = RowTableDirect<N, LF>;
   TW tw;
@@ -1336,7 +1354,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, true, false>;
+  using TW = PassTwiddles<P, C::THREADS, true, false, !NEXT>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if constexpr (TW::USES_LDS) __syncthreads();

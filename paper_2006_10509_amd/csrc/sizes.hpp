@@ -34,16 +34,26 @@ template <int N> struct ColCfg;
     static constexpr bool WAVE_SYNC = (C_ * T_ <= 64);                   \
   };
 
-// The shapes of lengths 512, 1024, 1080, 1920 and 2048 were chosen by timing
-// the GS loop on MI355X over candidate team sizes, radix orders and column
-// tile widths (single holograms and same-shape batches; paper_2006_10509_amd/
-// autotune.py automates the search); the rest are untuned defaults.
-// The tiled GS layout took a 1024^2 iteration from 21.8
-// to 20.1 us with tiles of 8 (4: 20.6, 16: 22.1) and is level at 2048^2
-// (tiles of 8; 16 is 1 % slower); rows of 64-thread teams cannot interleave
-// and keep row order, and so does 1920 x 1080, where tiles measured 3-6 %
-// slower.  Wider column tiles (C = 8: 64-byte row segments) win
-// where the frame still gives every CU a tile.
+// The shapes of lengths 512, 1024, 1080, 1920, 2048, 4096 and 8192 were
+// chosen by timing the GS loop on MI355X over candidate team sizes, radix
+// orders and column tile widths (single holograms and same-shape batches;
+// paper_2006_10509_amd/autotune.py automates the search); the rest are
+// untuned defaults.  The tiled GS layout took a 1024^2 iteration from 21.8
+// to 20.1 us and is level at 2048^2; rows of 64-thread teams cannot
+// interleave and keep row order, and so does 1920 x 1080, where tiles
+// measured 3-6 % slower.  Wider column tiles (C = 8: 64-byte row segments)
+// win where the frame still gives every CU a tile.
+// 4096^2 (Fresnel, L = 8, us per iteration): rows of 512-thread teams
+// (8·8·8·8, twiddles in registers) on tiles of 4 with one-column 512-thread
+// column workgroups 206; two 128-thread teams (16·16·16) 322; two 256-thread
+// teams with two-column 256-thread columns 241; tiles of 8: 230.
+// 8192^2: one 1024-thread row per workgroup in the palindromic order
+// 8·8·2·8·8 (22 twiddles in registers), tiles of 4: 1214; tiles of 2: 1382
+// (the row pass rewrites 1.76x its bytes: eight workgroups share every line),
+// 8 and 16: 1254 and 1262; row order 1530 (the column pass then reads 2.6x
+// its bytes: eight workgroups share every line of 8192 rows, more than the
+// L2 holds); 8·8·8·8·2 (twiddles read from memory) on tiles of 2: 1416;
+// 512-thread row teams: 1190-1254.
 //          N     rows/WG  T    FT  radices
 HG_ROW_CFG(16,    64,     4,  0,   4, 4)
 HG_ROW_CFG(32,    32,     8,  0,   4, 2, 4)
@@ -53,7 +63,7 @@ HG_ROW_CFG(256,   16,    16,  0,   16, 16)
 HG_ROW_CFG(512,   2,    64,  0,   8, 8, 8)
 HG_ROW_CFG(1024,   2,   128,  4,   8, 4, 4, 8)
 HG_ROW_CFG(2048,   2,   128,  8,   16, 8, 16)
-HG_ROW_CFG(4096,   2,   128,  4,   16, 16, 16)
+HG_ROW_CFG(4096,   1,   512,  4,   8, 8, 8, 8)
 HG_ROW_CFG(24,    32,     8,  0,   8, 3)
 HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)
 HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
@@ -64,7 +74,7 @@ HG_ROW_CFG(1280,   2,   128,  0,   16, 5, 16)
 HG_ROW_CFG(1536,   2,   128,  0,   8, 8, 8, 3)
 HG_ROW_CFG(2160,   4,   144,  0,   16, 3, 3, 3, 5)
 HG_ROW_CFG(3840,   2,   256,  0,   16, 16, 3, 5)
-HG_ROW_CFG(8192,   1,  1024,  0,   8, 8, 8, 8, 2)
+HG_ROW_CFG(8192,   1,  1024,  4,   8, 8, 2, 8, 8)
 
 //          N     cols/WG  T    radices
 HG_COL_CFG(16,    16,     4,   4, 4)
@@ -75,7 +85,7 @@ HG_COL_CFG(256,    8,    16,   16, 16)
 HG_COL_CFG(512,   8,    64,   8, 8, 8)
 HG_COL_CFG(1024,   2,   128,   8, 4, 4, 8)
 HG_COL_CFG(2048,   4,   128,   16, 8, 16)
-HG_COL_CFG(4096,   2,   128,   16, 16, 16)
+HG_COL_CFG(4096,   1,   512,   8, 8, 8, 8)
 HG_COL_CFG(24,    16,     8,   8, 3)
 HG_COL_CFG(60,    16,    16,   4, 3, 5)
 HG_COL_CFG(90,    16,    16,   2, 3, 3, 5)

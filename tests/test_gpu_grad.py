@@ -56,6 +56,8 @@ def gpu_loss_grad(planes, targets, phi):
     (120, 90, [0.45, None]),
     (512, 1024, [0.5, 0.4]),
     (1024, 1024, [0.40, 0.45, 0.50]),
+    (16, 8192, [0.45, 0.50]),
+    (4096, 16, [0.5, None]),
 ])
 def test_loss_and_gradient_match_oracle(h, w, distances):
     print(f"grad {h}x{w} planes={distances}", flush=True)
