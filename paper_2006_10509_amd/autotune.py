@@ -133,12 +133,12 @@ def radix_orders(n: int, current: Tuple[int, ...], limit: int) -> List[Tuple[int
 
 def row_shapes(n: int, cur: RowCfg, limit: int) -> List[RowCfg]:
     out = [cur]
-    for teams, t in itertools.product((1, 2, 4, 8), (64, 128, 256)):
+    for teams, t in itertools.product((1, 2, 4, 8), (64, 128, 256, 512)):
         threads = teams * t
         if threads % 64 or threads > 1024 or t > n:
             continue
-        # a tiled field needs interleaving teams: several rows of more than 64 threads
-        ft = cur[2] if (teams > 1 and t > 64 and t % max(cur[2], 1) == 0) else 0
+        # a tiled field needs teams that exchange through s_barrier (more than 64 threads)
+        ft = cur[2] if (t > 64 and t % max(cur[2], 1) == 0) else 0
         c = (teams, t, ft, cur[3])
         if c not in out:
             out.append(c)
@@ -147,7 +147,7 @@ def row_shapes(n: int, cur: RowCfg, limit: int) -> List[RowCfg]:
 
 def col_shapes(n: int, cur: ColCfg, limit: int) -> List[ColCfg]:
     out = [cur]
-    for cols, t in itertools.product((2, 4, 8, 16), (64, 128, 256)):
+    for cols, t in itertools.product((1, 2, 4, 8, 16), (64, 128, 256, 512)):
         threads = cols * t
         if threads % 64 or threads > 1024 or t > n:
             continue

@@ -62,7 +62,7 @@ HG_ROW_CFG(128,   16,    16,  0,   8, 2, 8)
 HG_ROW_CFG(256,   16,    16,  0,   16, 16)
 HG_ROW_CFG(512,   2,    64,  0,   8, 8, 8)
 HG_ROW_CFG(1024,   2,   128,  4,   8, 4, 4, 8)
-HG_ROW_CFG(2048,   2,   128,  8,   16, 8, 16)
+HG_ROW_CFG(2048,   1,   256,  8,   8, 4, 2, 4, 8)
 HG_ROW_CFG(4096,   1,   512,  4,   8, 8, 8, 8)
 HG_ROW_CFG(24,    32,     8,  0,   8, 3)
 HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)

@@ -49,6 +49,6 @@ def test_candidates_respect_the_kernel_constraints():
             assert _prod(r) == n and len(r) >= 2 and all(v in at.RADICES for v in r)
         for teams, t, ft, _ in at.row_shapes(n, rows[n], 12):
             assert (teams * t) % 64 == 0 and teams * t <= 1024
-            assert ft == 0 or (teams > 1 and t > 64 and t % ft == 0)
+            assert ft == 0 or (t > 64 and t % ft == 0)
         for c, t, _ in at.col_shapes(n, cols[n], 12):
             assert (c * t) % 64 == 0 and c * t <= 1024
