@@ -412,17 +412,31 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
     plain_ms = timed(lambda: hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream))
     plain_nmse = float(nm.item())
     pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, nmse=nm, stream=stream))
+    pair_nmse = float(nm.item())
+    # per-pass durations of the plain run (every launch executed TIMING_REPEATS
+    # times back to back): pass B moves 17 B/px; pass C, which after the first
+    # subframe also runs the next subframe's pass A, 32 B/px
+    npx = w.width * w.height
+    passes = {}
+    for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 17), ("pass_c", hg.HG_KERNEL_OSPR_C, 32)):
+        hg.hg_timing_begin(plan, kid, TIMING_REPEATS)
+        hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream)
+        total_ms, count = hg.hg_timing_end(plan)
+        us = total_ms * 1e3 / count
+        gbs = bpp * npx / (us * 1e-6) / 1e9
+        passes[name] = {"us_per_launch": round(us, 3), "algorithmic_bytes_per_px": bpp,
+                        "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return {"workload": w.name, "subframes": w.subframes, "plain_ms": round(plain_ms, 3),
             "plain_subframes_per_s": round(w.subframes / (plain_ms * 1e-3), 1), "plain_nmse": plain_nmse,
             "pairs_ms": round(pair_ms, 3), "pairs_subframes_per_s": round(w.subframes / (pair_ms * 1e-3), 1),
-            "pairs_nmse": float(nm.item())}
+            "pairs_nmse": pair_nmse, "passes": passes}
 
 
 def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
     """Direct binary search on a 1024x1024 binary Fourier hologram (target of
     the 1024^2 workload, random start and trial list from seed 12): trials/s.
-    Each trial is one pass over the replay field (rank-one update) plus a
-    one-workgroup decision."""
+    Each launch is one pass over the replay field (rank-one updates) that
+    decides the previous two trials and evaluates the next two."""
     import numpy as np
     w = wl.GS_FRESNEL_1024
     t = torch.from_numpy(w.inputs()[0]).cuda()
@@ -445,12 +459,19 @@ def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
     b.synchronize()
     ms = a.elapsed_time(b)
     rate = float(acc.float().mean().item())
+    # one pass over R per two trials: it reads R and T^2 and writes R back when
+    # either trial of the previous pair was accepted
+    launches = (n_trials + 1) // 2
+    pairs_written = float(acc[: n_trials // 2 * 2].view(-1, 2).amax(dim=1).float().mean().item())
     npx = w.height * w.width
-    trial_bytes = npx * (8 + 4 + 8 * rate)
+    pass_bytes = npx * (8 + 4 + 8 * pairs_written)
+    us_launch = ms * 1e3 / launches
+    gbs = pass_bytes / (us_launch * 1e-6) / 1e9
     return {"workload": "dbs_fourier_binary_1024x1024", "trials": n_trials, "ms": round(ms, 2),
             "trials_per_s": round(n_trials / (ms * 1e-3), 1), "us_per_trial": round(ms * 1e3 / n_trials, 2),
+            "trials_per_launch": 2, "us_per_launch": round(us_launch, 2),
             "accept_rate": round(rate, 4), "nmse_start": float(nm[0].item()), "nmse_end": float(nm[-1].item()),
-            "trial_pass_gbs": round(trial_bytes / (ms * 1e-3 / n_trials) / 1e9, 1)}
+            "pass_gbs": round(gbs, 1), "pass_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 SWEEP_SIZES = (256, 512, 1024, 2048, 4096, 8192)

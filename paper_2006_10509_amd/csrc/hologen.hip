@@ -1161,8 +1161,8 @@ size_t hg_search_workspace_bytes(hg_plan plan) {
   if (!plan) return 0;
   const size_t n = npix(plan);
   return align_up(n * sizeof(float2)) + 2 * align_up(n * sizeof(float)) + align_up(sizeof(Scalars)) +
-         align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double)) + align_up(2 * SEARCH_MAX_BLOCKS * sizeof(double)) +
-         align_up(2 * sizeof(SearchState));
+         align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double)) +
+         align_up(2 * SEARCH_SUMS * SEARCH_MAX_BLOCKS * sizeof(double)) + align_up(2 * sizeof(SearchState));
 }
 
 hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, const int32_t* trials,
@@ -1193,7 +1193,7 @@ hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, c
   double* stats = reinterpret_cast<double*>(b + off);
   off += align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   double* partials = reinterpret_cast<double*>(b + off);
-  off += align_up(2 * SEARCH_MAX_BLOCKS * sizeof(double));
+  off += align_up(2 * SEARCH_SUMS * SEARCH_MAX_BLOCKS * sizeof(double));
   SearchState* state = reinterpret_cast<SearchState*>(b + off);
 
   Workspace w{replay, sc, stats, nullptr, nullptr};
@@ -1247,12 +1247,15 @@ hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, c
   sa.nmse = nmse;
   sa.H = H;
   sa.W = W;
+  sa.hmask = (H & (H - 1)) == 0 ? (uint32_t)(H - 1) : 0u;
+  sa.wmask = (W & (W - 1)) == 0 ? (uint32_t)(W - 1) : 0u;
+  sa.wshift = sa.wmask ? (uint32_t)__builtin_ctz((unsigned)W) : 0u;
   sa.L = p->levels;
   const int nb = (int)std::min<size_t>((n + SEARCH_THREADS * 4 - 1) / (SEARCH_THREADS * 4), SEARCH_MAX_BLOCKS);
   hipLaunchKernelGGL(k_search_error, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa);
   hipLaunchKernelGGL(k_search_start, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, nb);
-  for (int k = 0; k < n_trials; ++k)
-    hipLaunchKernelGGL(k_search_step, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa, k);
+  for (int k = 0; k < n_trials; k += 2)
+    hipLaunchKernelGGL(k_search_step, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa, k, (int)n_trials);
   if (n_trials > 0)
     hipLaunchKernelGGL(k_search_finish, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, n_trials, nb);
   return launch_status("hg_pixel_search launch");

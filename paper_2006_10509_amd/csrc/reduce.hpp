@@ -56,6 +56,30 @@ __device__ __forceinline__ double block_sum_f64(double v, double* red) {
   return r;
 }
 
+// Three block sums at once, each through the same tree as block_sum_f64 (so
+// each equals what block_sum_f64 gives for it) with one set of barriers.
+// red: 3 * THREADS doubles.
+template <int THREADS>
+__device__ __forceinline__ void block_sum3_f64_tree(double& v0, double& v1, double& v2, double* red) {
+  red[threadIdx.x] = v0;
+  red[THREADS + threadIdx.x] = v1;
+  red[2 * THREADS + threadIdx.x] = v2;
+  __syncthreads();
+#pragma unroll
+  for (int s = THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red[THREADS + threadIdx.x] += red[THREADS + threadIdx.x + s];
+      red[2 * THREADS + threadIdx.x] += red[2 * THREADS + threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  v0 = red[0];
+  v1 = red[THREADS];
+  v2 = red[2 * THREADS];
+  __syncthreads();
+}
+
 // sum T^2, sum T^4, sum A^2 per workgroup (FP64), fixed order; with a
 // signal window (same order as the target, nonzero inside) the target sums
 // run over the window only.

@@ -60,7 +60,7 @@ def make_trials(h, w, levels, n, seed):
 
 @pytest.mark.parametrize("h,w,levels,fresnel,n", [
     (32, 32, 2, False, 400),
-    (24, 60, 4, True, 300),
+    (24, 60, 4, True, 301),
     (64, 64, 8, True, 200),
 ])
 def test_direct_search_matches_oracle(h, w, levels, fresnel, n):
@@ -94,6 +94,40 @@ def test_annealing_matches_oracle():
     if tie is None:
         assert np.array_equal(gpu[0], ref["levels"])
     assert (np.diff(ref["nmse"]) > 0).any()      # annealing took uphill moves
+
+
+@pytest.mark.parametrize("n,anneal", [(1, False), (2, False), (3, True), (41, False), (80, True)])
+def test_consecutive_trials_on_few_pixels_match_oracle(n, anneal):
+    """Trials drawn from four pixels, the same pixel as the trial before half
+    of the time, each flipping its pixel's current binary level (the trial
+    list is built with the oracle, so no trial is a no-op).  Two trials share
+    one launch, so this covers a trial whose pixel the trial before changed
+    (accepted or not) within the same and across launches, and odd counts."""
+    print(f"search few pixels n={n} anneal={anneal}", flush=True)
+    h, w = 32, 32
+    plan = plan_for(h, w, 2, False)
+    t = wl.target_amplitude(h, w, seed=31)
+    rng = np.random.default_rng(100 + n)
+    lev0 = rng.integers(0, 2, (h, w))
+    pix = rng.choice(h * w, 4, replace=False)
+    temp = (1e-2 * 0.97 ** np.arange(n)).astype(np.float32) if anneal else None
+    u = rng.uniform(0, 1, n).astype(np.float32) if anneal else None
+    kw = dict(temperature=None if temp is None else temp.astype(np.float64),
+              uniform=None if u is None else u.astype(np.float64))
+    trials, p = [], int(pix[0])
+    for k in range(n):
+        if k == 0 or rng.uniform() >= 0.5:
+            p = int(rng.choice(pix))
+        cur = oracle.pixel_search(t, lev0, 2, trials, **kw)["levels"] if trials else lev0
+        trials.append((p, 1 - int(cur.ravel()[p])))
+    gpu = run_search(plan, t, lev0, trials, temp, u)
+    ref = oracle.pixel_search(t, lev0, 2, trials, **kw)
+    tie = compare(gpu, ref)
+    if tie is None:
+        assert np.array_equal(gpu[0], ref["levels"])
+    if n >= 41:
+        again = [k for k in range(1, n) if trials[k][0] == trials[k - 1][0] and ref["accepted"][k - 1]]
+        assert again, "no trial followed an accepted trial on its pixel"
 
 
 def test_out_of_range_trials_are_rejected_no_ops():
