@@ -350,9 +350,12 @@ struct RowLds {
   using C = RowCfg<N>;
   using P = typename C::P;
   static_assert(tw_fits_reservation<P, C::THREADS>(), "one-order twiddles exceed the LDS reservation");
-  // a team's exchange region, padded to 4 mod 16 complex values so that the
-  // interleaved teams of one wavefront start on different LDS banks
-  static constexpr int TEAM = lds_len(N) + (20 - lds_len(N) % 16) % 16;
+  // a team's exchange region, padded so that the teams sharing a wavefront
+  // start on different LDS banks: 8 mod 16 complex values where tiled rows
+  // interleave two teams across the lanes (1024-point SLM pass 8.26 -> 7.88 us
+  // against 4 mod 16; 0, 12 mod 16 as slow as 4), else 4 mod 16
+  static constexpr int TEAM_OFF = C::FT ? 8 : 4;
+  static constexpr int TEAM = lds_len(N) + (TEAM_OFF + 16 - lds_len(N) % 16) % 16;
   static constexpr int TWF = C::TEAMS * TEAM;
   static constexpr int TAB = TWF + PassTwiddles<P, C::THREADS, true, true>::LDS_WORDS;
   // a per-column table is shared through LDS only when a thread's share of it
