@@ -769,12 +769,15 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   } else if constexpr (GENERAL) {
     if (a.q_out_set && a.qoy) qo.begin(a.qox, t);
   }
+  // this row's chirp values load with the tables, not after the transform,
+  // whose barriers would hold them back until the pointwise step needs them
+  const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
+  const float2 qoy_row = ((MP || GENERAL) && a.qoy) ? a.qoy[rt.y] : make_float2(1.f, 0.f);
   if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
   tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
-  const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   if constexpr (MP) {
     const bool fres_out = a.qoy != nullptr;
-    const float2 qoy = fres_out ? a.qoy[rt.y] : make_float2(1.f, 0.f);
+    const float2 qoy = qoy_row;
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
       if (fres) g = cmulconj(g, cmul(qy, qx.at(s, x)));
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_gs_row(GsRowArgs a) {
   } else {
     const bool out = rt.live && (a.phase_out || a.levels_out);
     const bool fres_out = a.q_out_set ? (a.qoy != nullptr) : fres;
-    const float2 qoy = a.q_out_set ? (fres_out ? a.qoy[rt.y] : make_float2(1.f, 0.f)) : qy;
+    const float2 qoy = a.q_out_set ? qoy_row : qy;
     for_layout<LF>(t, [&](int s, int x) {
       float2 g = v[s];
       float2 q = make_float2(1.f, 0.f);
@@ -890,17 +893,20 @@ __global__ __launch_bounds__((ColCfgSel<N, WIDE>::THREADS)) void k_gs_col(GsColA
   using TW = PassTwiddles<P, C::THREADS, true, BACK>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
-  if constexpr (TW::USES_LDS) __syncthreads();
-  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  float acc = 0.f;
-  double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+  // the error scalars are read here, not after the transform, so that their
+  // load does not wait behind its barriers
   const bool nm = WIN ? (a.wpartials != nullptr) : (a.partials != nullptr);
   const bool scaled = nm || MODE == COL_GRAD;
   const float sa = scaled ? a.sc->a : 0.f;
   const float sb = scaled ? a.sc->b : 0.f;
   const float sg = MODE == COL_GRAD ? a.sc->g : 0.f;
+  const float sc_win = WIN ? a.sc->c : 0.f;
+  if constexpr (TW::USES_LDS) __syncthreads();
+  tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+  float acc = 0.f;
+  double w1 = 0.0, w2 = 0.0, w3 = 0.0;
   if constexpr (WIN) {
-    const float sc = a.sc->c;
+    const float sc = sc_win;
     for_layout<L1>(t, [&](int s, int) {
       const float2 R = v[s];
       const float tv = tgt[s];
