@@ -1050,10 +1050,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) 
   const bool nfres = NEXT && a.qny != nullptr;
   if (fres) qx.begin(a.q1x, t);
   if (nfres) qn.begin(a.qnx, t);
-  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
-  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+  // this row's chirp values load with the tables (see k_gs_row)
   const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
   const float2 qny = nfres ? a.qny[rt.y] : make_float2(1.f, 0.f);
+  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
+  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
   if constexpr (!NEXT) {
     if (!rt.live) return;   // no barrier follows
   }

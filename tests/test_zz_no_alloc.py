@@ -69,3 +69,46 @@ def test_noalloc_rejects_plans_above_the_static_workspace():
     # a 2048^2 plan fits
     plan2 = hg.Plan(2048, 2048, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_PHASE, 0)
     assert plan2.workspace_bytes() <= hg.HG_NOALLOC_WORKSPACE_MAX
+
+
+def test_noalloc_call_captured_in_a_graph_replays_like_eager():
+    """The callers this entry point serves include code under HIP graph
+    capture.  A captured call replays with the eager call's results, four
+    times, with eager work between the replays that rewrites the shared static
+    workspace (a no-alloc call on another plan): the captured call depends on
+    nothing a previous call left there."""
+    torch = torch_mod()
+    h = w = 256
+    iters = 8
+    target, phi0 = wl.target_and_phase(h, w, seed=11)
+    plan = hg.Plan(w, h, hg.HG_FRESNEL, 532e-9, 8e-6, 0.5, hg.HG_PHASE_QUANTISED, 8)
+    t, p0 = dev(target), dev(phi0)
+    ph = p0.clone()
+    lv = torch.zeros((h, w), dtype=torch.uint8, device="cuda")
+    nm = torch.zeros(iters + 1, dtype=torch.float32, device="cuda")
+    hg.hg_gs_iterate_noalloc(plan, t, ph, iters, levels=lv, nmse=nm)
+    ref = (host(ph).copy(), host(lv).copy(), host(nm).copy())
+
+    h2 = w2 = 512
+    t2, q0 = (dev(x) for x in wl.target_and_phase(h2, w2, seed=12))
+    plan2 = hg.Plan(w2, h2, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_PHASE_QUANTISED, 4)
+
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ph.copy_(p0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            hg.hg_gs_iterate_noalloc(plan, t, ph, iters, levels=lv, nmse=nm)
+    torch.cuda.current_stream().wait_stream(side)
+    for replay in range(4):
+        ph.copy_(p0)
+        lv.zero_()
+        nm.zero_()
+        hg.hg_gs_iterate_noalloc(plan2, t2, q0.clone(), 3)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for name, r, g in zip(("phase", "levels", "nmse"), ref, (host(ph), host(lv), host(nm))):
+            assert np.array_equal(r.view(np.uint8), g.view(np.uint8)), (replay, name)
