@@ -34,8 +34,8 @@ template <int N> struct ColCfg;
     static constexpr bool WAVE_SYNC = (C_ * T_ <= 64);                   \
   };
 
-// The shapes of lengths 512, 1024, 1080, 1920, 2048, 4096 and 8192 were
-// chosen by timing the GS loop on MI355X over candidate team sizes, radix
+// The shapes of lengths 512, 1024, 1080, 1280, 1920, 2048, 2160, 3840, 4096
+// and 8192 were chosen by timing the GS loop on MI355X over candidate team sizes, radix
 // orders and column tile widths (single holograms and same-shape batches;
 // paper_2006_10509_amd/autotune.py automates the search); the rest are
 // untuned defaults.  The tiled GS layout took a 1024^2 iteration from 21.8
@@ -43,6 +43,12 @@ template <int N> struct ColCfg;
 // interleave and keep row order, and so does 1920 x 1080, where tiles
 // measured 3-6 % slower.  Wider column tiles (C = 8: 64-byte row segments)
 // win where the frame still gives every CU a tile.
+// Tuned with paper_2006_10509_amd/autotune.py on MI355X (Fourier, L = 4, us
+// per hologram-iteration): 1080 x 1920 in batches of 8, rows of 1920 as one
+// 256-thread team in the order 8·3·5·16: 30.3 -> 22.9 (a single hologram at
+// Fresnel L = 8: 56.7 -> 42.8 us per iteration); 2160 x 3840, one hologram:
+// rows 1 x 256 (16·5·16·3), columns 2 x 256 (16·3·5·3·3): 139.6 -> 113.0;
+// 1024 x 1280 in batches of 8, rows of 1280 on tiles of 2: 21.4 -> 12.2.
 // 4096^2 (Fresnel, L = 8, us per iteration): rows of 512-thread teams
 // (8·8·8·8, twiddles in registers) on tiles of 4 with one-column 512-thread
 // column workgroups 206; two 128-thread teams (16·16·16) 322; two 256-thread
@@ -69,11 +75,11 @@ HG_ROW_CFG(60,    16,    16,  0,   4, 3, 5)
 HG_ROW_CFG(90,    16,    16,  0,   2, 3, 3, 5)
 HG_ROW_CFG(120,   16,    16,  0,   8, 3, 5)
 HG_ROW_CFG(1080,   4,    64,  0,   8, 3, 3, 3, 5)
-HG_ROW_CFG(1920,   4,   128,  0,   16, 3, 5, 8)
-HG_ROW_CFG(1280,   2,   128,  0,   16, 5, 16)
+HG_ROW_CFG(1920,   1,   256,  0,   8, 3, 5, 16)
+HG_ROW_CFG(1280,   2,   128,  2,   16, 5, 16)
 HG_ROW_CFG(1536,   2,   128,  0,   8, 8, 8, 3)
 HG_ROW_CFG(2160,   4,   144,  0,   16, 3, 3, 3, 5)
-HG_ROW_CFG(3840,   2,   256,  0,   16, 16, 3, 5)
+HG_ROW_CFG(3840,   1,   256,  0,   16, 5, 16, 3)
 HG_ROW_CFG(8192,   1,  1024,  4,   8, 8, 2, 8, 8)
 
 //          N     cols/WG  T    radices
@@ -94,7 +100,7 @@ HG_COL_CFG(1080,   8,   120,   8, 3, 3, 3, 5)
 HG_COL_CFG(1920,   4,    64,   16, 8, 3, 5)
 HG_COL_CFG(1280,   4,   128,   16, 5, 16)
 HG_COL_CFG(1536,   4,   128,   8, 8, 8, 3)
-HG_COL_CFG(2160,   4,   144,   16, 3, 3, 3, 5)
+HG_COL_CFG(2160,   2,   256,   16, 3, 5, 3, 3)
 HG_COL_CFG(3840,   2,   256,   16, 16, 3, 5)
 HG_COL_CFG(8192,   2,   256,   8, 8, 8, 16)
 
