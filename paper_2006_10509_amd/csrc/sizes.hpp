@@ -34,8 +34,8 @@ template <int N> struct ColCfg;
     static constexpr bool WAVE_SYNC = (C_ * T_ <= 64);                   \
   };
 
-// The shapes of lengths 512, 1024, 1080, 1280, 1920, 2048, 2160, 3840, 4096
-// and 8192 were chosen by timing the GS loop on MI355X over candidate team sizes, radix
+// The shapes of lengths 512, 1024, 1080, 1280, 1536, 1920, 2048, 2160, 3840,
+// 4096 and 8192 were chosen by timing the GS loop on MI355X over candidate team sizes, radix
 // orders and column tile widths (single holograms and same-shape batches;
 // paper_2006_10509_amd/autotune.py automates the search); the rest are
 // untuned defaults.  The tiled GS layout took a 1024^2 iteration from 21.8
@@ -48,7 +48,10 @@ template <int N> struct ColCfg;
 // 256-thread team in the order 8·3·5·16: 30.3 -> 22.9 (a single hologram at
 // Fresnel L = 8: 56.7 -> 42.8 us per iteration); 2160 x 3840, one hologram:
 // rows 1 x 256 (16·5·16·3), columns 2 x 256 (16·3·5·3·3): 139.6 -> 113.0;
-// 1024 x 1280 in batches of 8, rows of 1280 on tiles of 2: 21.4 -> 12.2.
+// 1024 x 1280 in batches of 8, rows of 1280 on tiles of 2: 21.4 -> 12.2;
+// 1536 x 2048, one hologram, columns of 1536 as two 256-thread teams:
+// 45.5 -> 41.4.  A single 1080 x 1920 hologram found nothing better than
+// 1 % (38.6 -> 38.3, other radix orders).
 // 4096^2 (Fresnel, L = 8, us per iteration): rows of 512-thread teams
 // (8·8·8·8, twiddles in registers) on tiles of 4 with one-column 512-thread
 // column workgroups 206; two 128-thread teams (16·16·16) 322; two 256-thread
@@ -99,7 +102,7 @@ HG_COL_CFG(120,   16,    16,   8, 3, 5)
 HG_COL_CFG(1080,   8,   120,   8, 3, 3, 3, 5)
 HG_COL_CFG(1920,   4,    64,   16, 8, 3, 5)
 HG_COL_CFG(1280,   4,   128,   16, 5, 16)
-HG_COL_CFG(1536,   4,   128,   8, 8, 8, 3)
+HG_COL_CFG(1536,   2,   256,   8, 8, 8, 3)
 HG_COL_CFG(2160,   2,   256,   16, 3, 5, 3, 3)
 HG_COL_CFG(3840,   2,   256,   16, 16, 3, 5)
 HG_COL_CFG(8192,   2,   256,   8, 8, 8, 16)
