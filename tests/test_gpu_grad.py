@@ -8,7 +8,7 @@ four FP32 transforms (FFT2 then the adjoint FFT2), each within 1e-5 relative
 L2, plus pointwise products, so 1e-4 leaves a tenfold margin.  Adam
 trajectories: loss curves within 1e-3 relative over the first 50 steps
 (FP32 moments against FP64 ones drift slowly; beyond that only the final
-loss is compared, parity unpinned by any closed form)."""
+loss is compared: no closed form fixes a long trajectory)."""
 import numpy as np
 import pytest
 
