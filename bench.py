@@ -203,19 +203,40 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
     fin = losses[:, -1].cpu().numpy()
     # the same problems with plane-by-plane multi-plane GS (continuous phase),
     # 100 iterations of 3 steps each: summed final NMSE over the planes
+    # (all problems in one hg_gs_multiplane_batched call, and one call each)
     mws = hg.multiplane_workspace(planes)
     iters = 100
-    mnm = torch.empty((problems, iters * len(planes) + len(planes)), dtype=torch.float32, device="cuda")
+    n_mp = iters * len(planes) + len(planes)
+    mnm = torch.empty((problems, n_mp), dtype=torch.float32, device="cuda")
+    seq_ph = torch.stack([p0 for _, p0 in data])
     torch.cuda.synchronize()
     a.record(stream)
-    for bi, (tg, p0) in enumerate(data):
-        hg.hg_gs_multiplane(planes, tg, p0.clone(), iters, mws, nmse=mnm[bi], stream=stream)
+    for bi, (tg, _) in enumerate(data):
+        hg.hg_gs_multiplane(planes, tg, seq_ph[bi], iters, mws, nmse=mnm[bi], stream=stream)
     b.record(stream)
     b.synchronize()
-    mp_ms = a.elapsed_time(b)
-    mp_final = mnm[:, -len(planes):].sum(dim=1).cpu().numpy()
+    mp_seq_ms = a.elapsed_time(b)
+    bws = hg.multiplane_workspace_batched(planes, problems)
+    all_t = torch.stack([tg for tg, _ in data])
+    bnm = torch.empty((problems, n_mp), dtype=torch.float32, device="cuda")
+
+    def run_mp_batched():
+        ph = torch.stack([p0 for _, p0 in data])
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_gs_multiplane_batched(planes, all_t, ph, iters, bws, nmse=bnm, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b), ph
+
+    run_mp_batched()
+    mp_ms, mp_ph = run_mp_batched()
+    mp_same = bool(torch.equal(bnm, mnm) and torch.equal(mp_ph, seq_ph))
+    mp_final = bnm[:, -len(planes):].sum(dim=1).cpu().numpy()
     return {"workload": w.name, "problems": problems, "steps": w.steps, "planes": len(w.distances),
-            "multiplane_gs": {"iterations": iters, "ms": round(mp_ms, 2),
+            "multiplane_gs": {"iterations": iters, "ms": round(mp_ms, 2), "sequential_ms": round(mp_seq_ms, 2),
+                              "launch": "one hg_gs_multiplane_batched call for all problems",
+                              "batched_equals_sequential_bitwise": mp_same,
                               "final_loss_mean": float(mp_final.mean())},
             "launch": "one hg_grad_adam_batched call for all problems",
             "ms": round(ms, 2), "problem_steps_per_s": round(problems * w.steps / (ms * 1e-3), 1),

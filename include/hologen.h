@@ -206,7 +206,8 @@ hg_status hg_gs_iterate_noalloc(hg_plan plan, const float* target_amp, const flo
  * call per shape on one stream.  Item b uses target_amp + b H W,
  * phase + b H W, levels + b H W and nmse + b (iterations + 1); the
  * illumination (or NULL) is shared.  1 <= batch <= 65535 and
- * batch H W4 < 2^32 (W4 = W rounded up to a multiple of 4).  workspace: hg_workspace_bytes_batched(plan, batch)
+ * batch H Wt < 2^32 (Wt = W rounded up to a multiple of the plan's field
+ * tile width, at most 8).  workspace: hg_workspace_bytes_batched(plan, batch)
  * bytes (the fields of all items are resident together).  HG_FOURIER and
  * HG_FRESNEL plans only (HG_ANGULAR: HG_ERR_INVALID_ARGUMENT). */
 size_t hg_workspace_bytes_batched(hg_plan plan, int32_t batch);
@@ -241,6 +242,21 @@ size_t hg_multiplane_workspace_bytes(hg_plan plan, int32_t n_planes);
 hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float* target_amp,
                             const float* illumination, float* phase, uint8_t* levels, float* nmse,
                             int32_t iterations, void* workspace, hipStream_t stream);
+
+/* Multi-plane GS on a batch of same-shape problems in one launch per pass:
+ * exactly hg_gs_multiplane applied to each problem b < batch (bitwise the
+ * same results), every pass launched once over all problems.  Problem b uses
+ * target_amp + b n_planes H W ([batch][n_planes][H][W]), phase + b H W,
+ * levels + b H W and nmse + b (iterations n_planes + n_planes); the
+ * illumination (or NULL) is shared.  1 <= batch <= 65535 and batch H Wt <
+ * 2^32 (Wt as for hg_gs_iterate_batched).  workspace:
+ * hg_multiplane_workspace_bytes_batched(plans[0], n_planes, batch) bytes
+ * (0 for arguments out of range).  Errors as hg_gs_multiplane. */
+size_t hg_multiplane_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch);
+hg_status hg_gs_multiplane_batched(const hg_plan* planes, int32_t n_planes, int32_t batch,
+                                    const float* target_amp, const float* illumination, float* phase,
+                                    uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                                    hipStream_t stream);
 
 /* OSPR with real and imaginary subframe pairs, binary phase, on a HG_FOURIER
  * plan: one inverse transform per pair gives two subframes,

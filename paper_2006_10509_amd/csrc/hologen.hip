@@ -807,6 +807,141 @@ hg_status gs_validate(hg_plan p, const float* target_amp, const float* phase, in
   return HG_OK;
 }
 
+// Multi-plane GS on `batch` same-shape problems (batch 1: hg_gs_multiplane).
+// Problem b takes target_amp + b P N, phase and levels + b N and nmse + b (P
+// iterations + P); its field, Scalars, partial sums and tiled targets lie at
+// the item strides of grad_layout, and every pass is one launch over all
+// problems (gridDim.y), with the wide column configuration where there is one.
+hg_status multiplane_run(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
+                         const float* illumination, float* phase, uint8_t* levels, float* nmse, int32_t iterations,
+                         void* workspace, hipStream_t stream, const char* what) {
+  hg_status st = validate_planes(planes, n_planes);
+  if (st != HG_OK) return st;
+  st = gs_validate(planes[0], target_amp, phase, iterations, workspace);
+  if (st != HG_OK) return st;
+  if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
+  if ((size_t)batch * field_elems(planes[0]) > (size_t)UINT32_MAX)
+    return fail(HG_ERR_INVALID_ARGUMENT, "batch * height * (padded) width must be below 2^32");
+  for (int j = 1; j < n_planes; ++j)
+    if (planes[j]->desc.modulation != planes[0]->desc.modulation || planes[j]->levels != planes[0]->levels)
+      return fail(HG_ERR_INVALID_ARGUMENT, "all planes must have the same modulation and levels");
+  if (planes[0]->desc.modulation == HG_AMPLITUDE)
+    return fail(HG_ERR_INVALID_ARGUMENT, std::string(what) + " takes phase-only plans");
+  const int P = n_planes;
+  hg_plan p0 = planes[0];
+  const int W = p0->desc.width, H = p0->desc.height;
+  const size_t n = npix(p0);
+  const GradLayout L = grad_layout(p0, P, batch);
+  char* ws = static_cast<char*>(workspace);
+  float2* field = reinterpret_cast<float2*>(ws);
+  Scalars* sc = reinterpret_cast<Scalars*>(ws + L.sc);
+  double* stats = reinterpret_cast<double*>(ws + L.stats);
+  float* partials = reinterpret_cast<float*>(ws + L.partials);
+  const RowKernels& rk = p0->row->row;
+  const ColLaunch cl = col_launch(p0, batch);
+  const int slots = cl.slots();   // per-column error partials of one step
+  const uint32_t tiled_n = (uint32_t)slots * H;
+  const int nb = stats_blocks(n);
+  const size_t steps_total = (size_t)iterations * P + P;   // nmse entries per problem
+  for (int b = 0; b < batch; ++b)
+    for (int j = 0; j < P; ++j) {
+      const float* tj = target_amp + ((size_t)b * P + j) * n;
+      float* tiled = reinterpret_cast<float*>(ws + L.target + ((size_t)b * P + j) * L.target_stride);
+      hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cl.cols,
+                         tiled_n);
+      if (nmse) {
+        hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, illumination, n, stats);
+        hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n,
+                           illumination ? 1 : 0, 0.0, (double)n, sc + (size_t)b * P + j);
+      }
+    }
+  auto chirp_of = [&](int j, const float2*& qy, const float2*& qx) {
+    const bool fres = planes[j]->desc.propagation == HG_FRESNEL;
+    qy = fres ? planes[j]->q1y : nullptr;
+    qx = fres ? planes[j]->q1x : nullptr;
+  };
+  GsRowArgs ra{};
+  ra.ft = p0->ft;
+  ra.field = field;
+  ra.illum = illumination;
+  ra.H = H;
+  ra.px = (uint32_t)n;
+  ra.fpx = (uint32_t)field_elems(p0);
+  ra.slm.lvl_tab = p0->lvl_tab;
+  ra.slm.levels = p0->levels;
+  ra.slm.inv_delta = p0->levels ? (float)((double)p0->levels / (2.0 * M_PI)) : 0.0f;
+  ra.slm.inv_delta_f64 = p0->levels ? (double)p0->levels / (2.0 * M_PI) : 0.0;
+  ra.slm.half_step = p0->levels ? make_float2((float)std::cos(M_PI / p0->levels), (float)std::sin(M_PI / p0->levels))
+                                : make_float2(1.0f, 0.0f);
+  ra.tw = p0->tw_row[0];
+  ra.twr = p0->tw_row[1];
+  GsColArgs ca{};
+  ca.ft = p0->ft;
+  ca.field = field;
+  ca.W = W;
+  ca.H = H;
+  ca.tw = p0->tw_col[0];
+  ca.twr = p0->tw_col[1];
+  ca.px = (uint32_t)field_elems(p0);
+  ca.target_stride = (uint32_t)((size_t)P * L.target_stride / sizeof(float));
+  ca.sc_stride = (uint32_t)P;
+  ca.partial_stride = (uint32_t)L.partial_stride;
+  const dim3 rows(p0->row_blocks, batch), tiles(cl.blocks, batch);
+  const int mp_mode = gs_mode_index(p0->levels == 0 ? GS_CONT
+                                    : (p0->levels == 2 || p0->levels == 4 || p0->levels == 8) ? p0->levels
+                                                                                                : GS_QATAN);
+
+  chirp_of(0, ra.q1y, ra.q1x);
+  ra.phase0 = phase;
+  ra.phase_out = iterations == 0 ? phase : nullptr;
+  ra.levels_out = iterations == 0 ? levels : nullptr;
+  hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, ra);
+  const int steps = iterations * P;
+  int chunk0 = 0;
+  auto flush = [&](int upto) {   // reduce the partials of steps chunk0..upto
+    hipLaunchKernelGGL(k_nmse_reduce_planes, dim3(upto - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
+                       (const float*)partials, slots, (const Scalars*)sc, P, chunk0, nmse + chunk0,
+                       L.partial_stride, steps_total);
+    chunk0 = upto + 1;
+  };
+  for (int s = 0; s < steps; ++s) {
+    const int j = s % P;
+    ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
+    ca.sc = sc + j;
+    ca.partials = nmse ? partials + (size_t)(s - chunk0) * slots : nullptr;
+    hipLaunchKernelGGL(cl.gs_col, tiles, dim3(cl.threads), cl.lds, stream, ca);
+    if (nmse && s - chunk0 == kNmseChunk - 1) flush(s);
+    chirp_of(j, ra.q1y, ra.q1x);
+    ra.q_out_set = 1;
+    chirp_of((j + 1) % P, ra.qoy, ra.qox);
+    ra.phase_out = s == steps - 1 ? phase : nullptr;
+    ra.levels_out = s == steps - 1 ? levels : nullptr;
+    // steady-state variant unless the step needs illumination or produces outputs
+    void (*row)(GsRowArgs) =
+        (illumination || ra.phase_out || ra.levels_out) ? rk.gs_row_general : rk.gs_row_mp[mp_mode];
+    hipLaunchKernelGGL(row, rows, dim3(rk.threads), rk.lds, stream, ra);
+  }
+  if (nmse) {
+    // the final state at every plane: its start pass for that plane's chirp, then an NMSE-only pass
+    GsRowArgs fa = ra;
+    fa.q_out_set = 0;
+    fa.phase0 = phase;
+    fa.phase_out = nullptr;
+    fa.levels_out = nullptr;
+    for (int j = 0; j < P; ++j) {
+      const int s = steps + j;
+      chirp_of(j, fa.q1y, fa.q1x);
+      hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, fa);
+      ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
+      ca.sc = sc + j;
+      ca.partials = partials + (size_t)(s - chunk0) * slots;
+      hipLaunchKernelGGL(cl.gs_col_nmse, tiles, dim3(cl.threads), cl.lds, stream, ca);
+      if (s - chunk0 == kNmseChunk - 1 || j == P - 1) flush(s);
+    }
+  }
+  return launch_status((std::string(what) + " launch").c_str());
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1262,128 +1397,29 @@ hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, c
 }
 
 size_t hg_multiplane_workspace_bytes(hg_plan plan, int32_t n_planes) {
-  if (!plan || n_planes < 1 || n_planes > kMaxPlanes) return 0;
-  return grad_layout(plan, n_planes).total;
+  return hg_multiplane_workspace_bytes_batched(plan, n_planes, 1);
+}
+
+size_t hg_multiplane_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch) {
+  if (!plan || n_planes < 1 || n_planes > kMaxPlanes || batch < 1 || batch > 65535) return 0;
+  return grad_layout(plan, n_planes, batch).total;
 }
 
 hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float* target_amp,
                             const float* illumination, float* phase, uint8_t* levels, float* nmse,
                             int32_t iterations, void* workspace, hipStream_t stream) {
-  hg_status st = validate_planes(planes, n_planes);
-  if (st != HG_OK) return st;
-  st = gs_validate(planes[0], target_amp, phase, iterations, workspace);
-  if (st != HG_OK) return st;
-  for (int j = 1; j < n_planes; ++j)
-    if (planes[j]->desc.modulation != planes[0]->desc.modulation || planes[j]->levels != planes[0]->levels)
-      return fail(HG_ERR_INVALID_ARGUMENT, "all planes must have the same modulation and levels");
-  if (planes[0]->desc.modulation == HG_AMPLITUDE)
-    return fail(HG_ERR_INVALID_ARGUMENT, "hg_gs_multiplane takes phase-only plans");
-  const int P = n_planes;
-  hg_plan p0 = planes[0];
-  const int W = p0->desc.width, H = p0->desc.height;
-  const size_t n = npix(p0);
-  const GradLayout L = grad_layout(p0, P);
-  char* ws = static_cast<char*>(workspace);
-  float2* field = reinterpret_cast<float2*>(ws);
-  Scalars* sc = reinterpret_cast<Scalars*>(ws + L.sc);
-  double* stats = reinterpret_cast<double*>(ws + L.stats);
-  float* partials = reinterpret_cast<float*>(ws + L.partials);
-  const RowKernels& rk = p0->row->row;
-  const ColKernels& ck = p0->col->col;
-  const int cols = ck.cols;
-  const int slots = p0->col_blocks * cols;   // per-column error partials of one step
-  const uint32_t tiled_n = (uint32_t)slots * H;
-  const int nb = stats_blocks(n);
-  for (int j = 0; j < P; ++j) {
-    const float* tj = target_amp + (size_t)j * n;
-    float* tiled = reinterpret_cast<float*>(ws + L.target + (size_t)j * L.target_stride);
-    hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cols,
-                       tiled_n);
-    if (nmse) {
-      hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, illumination, n, stats);
-      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n,
-                         illumination ? 1 : 0, 0.0, (double)n, sc + j);
-    }
-  }
-  auto chirp_of = [&](int j, const float2*& qy, const float2*& qx) {
-    const bool fres = planes[j]->desc.propagation == HG_FRESNEL;
-    qy = fres ? planes[j]->q1y : nullptr;
-    qx = fres ? planes[j]->q1x : nullptr;
-  };
-  GsRowArgs ra{};
-  ra.ft = p0->ft;
-  ra.field = field;
-  ra.illum = illumination;
-  ra.H = H;
-  ra.slm.lvl_tab = p0->lvl_tab;
-  ra.slm.levels = p0->levels;
-  ra.slm.inv_delta = p0->levels ? (float)((double)p0->levels / (2.0 * M_PI)) : 0.0f;
-  ra.slm.inv_delta_f64 = p0->levels ? (double)p0->levels / (2.0 * M_PI) : 0.0;
-  ra.slm.half_step = p0->levels ? make_float2((float)std::cos(M_PI / p0->levels), (float)std::sin(M_PI / p0->levels))
-                                : make_float2(1.0f, 0.0f);
-  ra.tw = p0->tw_row[0];
-  ra.twr = p0->tw_row[1];
-  GsColArgs ca{};
-  ca.ft = p0->ft;
-  ca.field = field;
-  ca.W = W;
-  ca.H = H;
-  ca.tw = p0->tw_col[0];
-  ca.twr = p0->tw_col[1];
-  const dim3 rows(p0->row_blocks), tiles(p0->col_blocks);
-  const int mp_mode = gs_mode_index(p0->levels == 0 ? GS_CONT
-                                    : (p0->levels == 2 || p0->levels == 4 || p0->levels == 8) ? p0->levels
-                                                                                                : GS_QATAN);
-
-  chirp_of(0, ra.q1y, ra.q1x);
-  ra.phase0 = phase;
-  ra.phase_out = iterations == 0 ? phase : nullptr;
-  ra.levels_out = iterations == 0 ? levels : nullptr;
-  hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, ra);
-  const int steps = iterations * P;
-  int chunk0 = 0;
-  auto flush = [&](int upto) {   // reduce the partials of steps chunk0..upto
-    hipLaunchKernelGGL(k_nmse_reduce_planes, dim3(upto - chunk0 + 1), dim3(STATS_THREADS), 0, stream,
-                       (const float*)partials, slots, (const Scalars*)sc, P, chunk0, nmse + chunk0);
-    chunk0 = upto + 1;
-  };
-  for (int s = 0; s < steps; ++s) {
-    const int j = s % P;
-    ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
-    ca.sc = sc + j;
-    ca.partials = nmse ? partials + (size_t)(s - chunk0) * slots : nullptr;
-    hipLaunchKernelGGL(ck.gs_col, tiles, dim3(ck.threads), ck.lds, stream, ca);
-    if (nmse && s - chunk0 == kNmseChunk - 1) flush(s);
-    chirp_of(j, ra.q1y, ra.q1x);
-    ra.q_out_set = 1;
-    chirp_of((j + 1) % P, ra.qoy, ra.qox);
-    ra.phase_out = s == steps - 1 ? phase : nullptr;
-    ra.levels_out = s == steps - 1 ? levels : nullptr;
-    // steady-state variant unless the step needs illumination or produces outputs
-    void (*row)(GsRowArgs) =
-        (illumination || ra.phase_out || ra.levels_out) ? rk.gs_row_general : rk.gs_row_mp[mp_mode];
-    hipLaunchKernelGGL(row, rows, dim3(rk.threads), rk.lds, stream, ra);
-  }
-  if (nmse) {
-    // the final state at every plane: its start pass for that plane's chirp, then an NMSE-only pass
-    GsRowArgs fa = ra;
-    fa.q_out_set = 0;
-    fa.phase0 = phase;
-    fa.phase_out = nullptr;
-    fa.levels_out = nullptr;
-    for (int j = 0; j < P; ++j) {
-      const int s = steps + j;
-      chirp_of(j, fa.q1y, fa.q1x);
-      hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, fa);
-      ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
-      ca.sc = sc + j;
-      ca.partials = partials + (size_t)(s - chunk0) * slots;
-      hipLaunchKernelGGL(ck.gs_col_nmse, tiles, dim3(ck.threads), ck.lds, stream, ca);
-      if (s - chunk0 == kNmseChunk - 1 || j == P - 1) flush(s);
-    }
-  }
-  return launch_status("hg_gs_multiplane launch");
+  return multiplane_run(planes, n_planes, 1, target_amp, illumination, phase, levels, nmse, iterations, workspace,
+                        stream, "hg_gs_multiplane");
 }
+
+hg_status hg_gs_multiplane_batched(const hg_plan* planes, int32_t n_planes, int32_t batch,
+                                    const float* target_amp, const float* illumination, float* phase,
+                                    uint8_t* levels, float* nmse, int32_t iterations, void* workspace,
+                                    hipStream_t stream) {
+  return multiplane_run(planes, n_planes, batch, target_amp, illumination, phase, levels, nmse, iterations,
+                        workspace, stream, "hg_gs_multiplane_batched");
+}
+
 
 size_t hg_grad_workspace_bytes(hg_plan plan, int32_t n_planes) {
   return hg_grad_workspace_bytes_batched(plan, n_planes, 1);

@@ -189,11 +189,17 @@ __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce(const float* __re
 }
 
 // nmse[b] = sum_wg partials[b][wg] / denom of plane (first + b) % planes: the
-// steps of a plane-by-plane multi-plane loop, one workgroup per step.
+// steps of a plane-by-plane multi-plane loop, one workgroup per step;
+// blockIdx.y selects the problem of a batch (partials, Scalars and nmse
+// advance by partial_stride, planes and nmse_stride).
 __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce_planes(const float* __restrict__ partials, int nwg,
                                                                       const Scalars* __restrict__ sc, int planes,
-                                                                      int first, float* __restrict__ nmse) {
+                                                                      int first, float* __restrict__ nmse,
+                                                                      size_t partial_stride, size_t nmse_stride) {
   __shared__ double red[STATS_THREADS];
+  partials += blockIdx.y * partial_stride;
+  sc += blockIdx.y * (size_t)planes;
+  nmse += blockIdx.y * nmse_stride;
   const float* p = partials + (size_t)blockIdx.x * nwg;
   double s = 0.0;
   for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];

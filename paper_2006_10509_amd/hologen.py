@@ -43,6 +43,7 @@ HG_KERNEL_PROP_COL = 7
 EXPORTED = ("hg_plan_create", "hg_plan_destroy", "hg_workspace_bytes", "hg_length_supported",
             "hg_propagate", "hg_gs_iterate", "hg_gs_iterate_window", "hg_gs_iterate_noalloc", "hg_workspace_bytes_batched", "hg_gs_iterate_batched",
             "hg_multiplane_workspace_bytes", "hg_gs_multiplane",
+            "hg_multiplane_workspace_bytes_batched", "hg_gs_multiplane_batched",
             "hg_ospr", "hg_ospr_pairs", "hg_search_workspace_bytes", "hg_pixel_search",
             "hg_grad_workspace_bytes", "hg_grad", "hg_grad_adam",
             "hg_grad_workspace_bytes_batched", "hg_grad_batched", "hg_grad_adam_batched",
@@ -109,6 +110,10 @@ def library() -> ctypes.CDLL:
     lib.hg_multiplane_workspace_bytes.restype = sz
     lib.hg_gs_multiplane.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.hg_gs_multiplane.restype = i32
+    lib.hg_multiplane_workspace_bytes_batched.argtypes = [vp, i32, i32]
+    lib.hg_multiplane_workspace_bytes_batched.restype = sz
+    lib.hg_gs_multiplane_batched.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.hg_gs_multiplane_batched.restype = i32
     lib.hg_search_workspace_bytes.argtypes = [vp]
     lib.hg_search_workspace_bytes.restype = sz
     lib.hg_pixel_search.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -337,6 +342,32 @@ def hg_gs_multiplane(planes, target_amp, phase, iterations: int, workspace, illu
         _ptr(illumination, torch.float32, shape, "illumination", optional=True),
         _ptr(phase, torch.float32, shape, "phase"), _ptr(levels, torch.uint8, shape, "levels", optional=True),
         _ptr(nmse, torch.float32, (iterations * P + P,), "nmse", optional=True), int(iterations),
+        _workspace(workspace, need), _stream(stream)))
+
+
+def multiplane_workspace_batched(planes, batch: int, device="cuda"):
+    import torch
+    planes, _ = _plans(planes)
+    n = int(library().hg_multiplane_workspace_bytes_batched(planes[0].handle, len(planes), int(batch)))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def hg_gs_multiplane_batched(planes, target_amp, phase, iterations: int, workspace, illumination=None,
+                             levels=None, nmse=None, stream=None) -> None:
+    """Multi-plane GS on a batch of problems: target_amp [batch, n_planes, H, W],
+    phase and levels [batch, H, W], nmse [batch, iterations * n_planes + n_planes]."""
+    import torch
+    planes, arr = _plans(planes)
+    P = len(planes)
+    batch = int(phase.shape[0])
+    shape = (planes[0].height, planes[0].width)
+    need = int(library().hg_multiplane_workspace_bytes_batched(planes[0].handle, P, batch))
+    _check(library().hg_gs_multiplane_batched(
+        arr, P, batch, _ptr(target_amp, torch.float32, (batch, P) + shape, "target_amp"),
+        _ptr(illumination, torch.float32, shape, "illumination", optional=True),
+        _ptr(phase, torch.float32, (batch,) + shape, "phase"),
+        _ptr(levels, torch.uint8, (batch,) + shape, "levels", optional=True),
+        _ptr(nmse, torch.float32, (batch, iterations * P + P), "nmse", optional=True), int(iterations),
         _workspace(workspace, need), _stream(stream)))
 
 

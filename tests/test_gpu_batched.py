@@ -143,3 +143,89 @@ def test_mix_shape_class_item_against_oracle(h, w, iters):
     i = 1            # the class's last item: the second of its batch
     restarts = check_quantised_segments(targets[i], phases[i], iters, 4, None, None, nm[i], states[i])
     print(f"oracle restarted at states {restarts}")
+
+
+# ---------------------------------------------------------------------------
+# batched multi-plane GS (hg_gs_multiplane_batched)
+# ---------------------------------------------------------------------------
+def mp_planes(h, w, specs, levels):
+    mod = hg.HG_PHASE_QUANTISED if levels else hg.HG_PHASE
+    return [hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, mod, levels) if z is None else
+            hg.Plan(w, h, hg.HG_FRESNEL, 532e-9, 8e-6, z, mod, levels) for z in specs]
+
+
+def mp_problems(h, w, P, batch, seed0):
+    t = np.stack([np.stack([wl.target_amplitude(h, w, seed=seed0 + 10 * b + j) for j in range(P)])
+                  for b in range(batch)])
+    ph = np.stack([wl.uniform_phase(h, w, seed=seed0 + 10 * b + 9) for b in range(batch)])
+    return t, ph
+
+
+@pytest.mark.parametrize("h,w,specs,levels,batch,iters", [
+    (256, 256, [0.40, 0.45, 0.50], 8, 3, 4),
+    (90, 120, [0.5, None], 0, 4, 5),
+    (1024, 1024, [0.45, 0.50], 4, 2, 2),     # four-column workgroups for the batch
+    (64, 64, [None, 0.5, None], 3, 5, 3),
+])
+def test_batched_multiplane_equals_single_calls_bitwise(h, w, specs, levels, batch, iters):
+    """Every problem of one batched multi-plane call (phase, level map, the
+    error of every step and of the final state at every plane) is bitwise
+    the single-problem hg_gs_multiplane call."""
+    print(f"batched multiplane {h}x{w} planes={specs} L={levels} batch={batch} it={iters}", flush=True)
+    torch = torch_mod()
+    planes = mp_planes(h, w, specs, levels)
+    P = len(planes)
+    t, ph0 = mp_problems(h, w, P, batch, 40)
+    ph = dev(ph0.copy())
+    lv = torch.zeros((batch, h, w), dtype=torch.uint8, device="cuda")
+    nm = torch.zeros((batch, iters * P + P), dtype=torch.float32, device="cuda")
+    hg.hg_gs_multiplane_batched(planes, dev(t), ph, iters, hg.multiplane_workspace_batched(planes, batch),
+                                levels=lv, nmse=nm)
+    ph, lv, nm = host(ph), host(lv), host(nm)
+    for b in range(batch):
+        p1 = dev(ph0[b].copy())
+        l1 = torch.zeros((h, w), dtype=torch.uint8, device="cuda")
+        n1 = torch.zeros(iters * P + P, dtype=torch.float32, device="cuda")
+        hg.hg_gs_multiplane(planes, dev(t[b]), p1, iters, hg.multiplane_workspace(planes), levels=l1, nmse=n1)
+        assert np.array_equal(ph[b].view(np.uint32), host(p1).view(np.uint32)), b
+        assert np.array_equal(lv[b], host(l1)), b
+        assert np.array_equal(nm[b].view(np.uint32), host(n1).view(np.uint32)), b
+
+
+def test_batched_multiplane_item_against_oracle():
+    """One problem of a batch against the FP64 oracle: the error of every step
+    within 1e-4 relative and the continuous phase at the continuous-phase bar."""
+    from gpu_util import phase_parity
+    torch = torch_mod()
+    h = w = 128
+    zs = (0.40, 0.45, 0.50)
+    planes = mp_planes(h, w, list(zs), 0)
+    batch, iters = 3, 2
+    t, ph0 = mp_problems(h, w, 3, batch, 70)
+    ph = dev(ph0.copy())
+    nm = torch.zeros((batch, iters * 3 + 3), dtype=torch.float32, device="cuda")
+    hg.hg_gs_multiplane_batched(planes, dev(t), ph, iters, hg.multiplane_workspace_batched(planes, batch), nmse=nm)
+    b = 2
+    ref = oracle.gs_multiplane(list(t[b]), ph0[b], iters,
+                               [dict(wavelength=532e-9, pitch=8e-6, distance=z) for z in zs])
+    rel = np.abs(host(nm)[b] - np.array(ref["nmse"])) / np.array(ref["nmse"])
+    assert rel.max() <= 1e-4, (rel.max(), int(rel.argmax()))
+    l2, frac = phase_parity(host(ph)[b], ref["phase"])
+    assert l2 <= 1e-4 and frac <= 1e-4, (l2, frac)
+
+
+def test_batched_multiplane_argument_checks():
+    torch = torch_mod()
+    h = w = 64
+    planes = mp_planes(h, w, [0.5, None], 4)
+    t = torch.ones((2, 2, h, w), dtype=torch.float32, device="cuda")
+    ph = torch.zeros((2, h, w), dtype=torch.float32, device="cuda")
+    assert hg.library().hg_multiplane_workspace_bytes_batched(planes[0].handle, 2, 0) == 0
+    assert hg.library().hg_multiplane_workspace_bytes_batched(planes[0].handle, 2, 65536) == 0
+    assert (hg.library().hg_multiplane_workspace_bytes_batched(planes[0].handle, 2, 1) ==
+            hg.library().hg_multiplane_workspace_bytes(planes[0].handle, 2))
+    with pytest.raises(ValueError):   # workspace for one problem, two in the call
+        hg.hg_gs_multiplane_batched(planes, t, ph, 1, hg.multiplane_workspace(planes))
+    amp = [hg.Plan(w, h, hg.HG_FOURIER, 0.0, 0.0, 0.0, hg.HG_AMPLITUDE, 0)]
+    with pytest.raises(hg.HologenError):
+        hg.hg_gs_multiplane_batched(amp, t[:, :1].contiguous(), ph, 1, hg.multiplane_workspace_batched(amp, 2))
