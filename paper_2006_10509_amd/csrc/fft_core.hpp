@@ -530,7 +530,7 @@ constexpr int TW_LDS_MAX_WORDS = 8704;
 
 // Twiddles of one pass kernel for the transform orders it runs (USE_F: the
 // forward radix order, USE_R: the reversed one).  When every set it needs
-// fits in registers (tw_in_regs), each thread loads its own
+// fits in registers (IN_REGS below), each thread loads its own
 // entries from the global twiddle image straight into registers: coalesced
 // loads that go out with the kernel's data loads and need neither LDS nor a
 // barrier.  Larger sets are copied into the workgroup's LDS at `lds_img`

@@ -837,8 +837,8 @@ struct GsColArgs {
   // tiled-target floats, Scalars, partial floats
   uint32_t px, target_stride, sc_stride, partial_stride;
   int ft;                     // field layout (ColField)
-  // (offsets in 64 bits: a batch of multi-plane problems spans more than
-  // 2^32 target and partial-sum floats before its fields do)
+  // (offsets in 64 bits: a batch of multi-plane problems can span more than
+  // 2^32 target and partial-sum floats while its fields stay below that)
   __device__ __forceinline__ void select_item() {
     const size_t b = blockIdx.y;
     field += b * px;
