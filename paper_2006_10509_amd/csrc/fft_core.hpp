@@ -465,12 +465,14 @@ template <class P, bool REV>
 using TwLdsFor = TwLds<P, P::PALINDROME ? false : REV>;
 
 // Twiddle registers worth holding for a whole transform: up to 16 complex
-// values (32 VGPRs), or more while twiddles and data together take at most 32
-// complex values (64 VGPRs; e.g. 22 twiddles beside 8 data values).  Larger
-// sets stay in LDS and are read at each use, since holding them would push
-// the transform's registers into AGPR spills.
+// values (32 VGPRs), or more while twiddles and data together take at most 40
+// complex values (80 VGPRs; e.g. 22 twiddles beside 8 data values at 8192, or
+// beside 16 in the 2048-point column pass, whose LDS then holds the data
+// alone: OSPR's 2048^2 column pass 23.1 -> 17.0 us).  Larger sets stay in
+// LDS and are read at each use, since holding them would push the
+// transform's registers into AGPR spills.
 constexpr int TW_REG_MAX = 16;
-constexpr int TW_DATA_REG_MAX = 32;
+constexpr int TW_DATA_REG_MAX = 40;
 
 // Whether the kernels of plan P that run both transform orders hold their
 // twiddles in registers (PassTwiddles with DATA_REGS), so that no LDS is
