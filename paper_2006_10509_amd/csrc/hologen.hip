@@ -104,8 +104,8 @@ hipError_t prepare_kernels(const LengthEntry* e) {
     chk(allow_lds(e->col_wide.gs_col_nmse, e->col_wide.lds));
     chk(allow_lds(e->col_wide.grad_col, e->col_wide.lds));
   }
-  chk(allow_lds(e->col.ospr_b, e->col.lds));
-  chk(allow_lds(e->col.ospr_b_pair, e->col.lds));
+  chk(allow_lds(e->col.ospr_b, e->col.ospr_lds));
+  chk(allow_lds(e->col.ospr_b_pair, e->col.ospr_lds));
   chk(allow_lds(e->row.grad_row, e->row.lds));
   chk(allow_lds(e->row.grad_row_next, e->row.lds));
   chk(allow_lds(e->col.grad_col, e->col.lds));
@@ -180,6 +180,7 @@ struct hg_plan_s {
   // column count, which also divides the field's tile width)
   bool wide_ok = false;
   int col_blocks_wide = 0;
+  int ospr_col_blocks = 0;   // workgroups of OSPR's column pass
   // per-column error partials of one state: the padded width of the widest
   // column configuration
   int col_slots = 0;
@@ -1042,10 +1043,14 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   }
   p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
   p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
+  p->ospr_col_blocks = (W + p->col->col.ospr_cols - 1) / p->col->col.ospr_cols;
   // Tiled where the row kernels are compiled for a tile width that the column
-  // pass's tile width divides (whole-line accesses on both passes); row
-  // order elsewhere.
-  p->ft = p->row->row.ft != 0 && p->row->row.ft % p->col->col.cols == 0 ? p->row->row.ft : 0;
+  // passes' widths divide (whole-line accesses on both passes); row order
+  // elsewhere.
+  p->ft = p->row->row.ft != 0 && p->row->row.ft % p->col->col.cols == 0 &&
+                  p->row->row.ft % p->col->col.ospr_cols == 0
+              ? p->row->row.ft
+              : 0;
   const size_t n = (size_t)W * H;
   {
     const int cw = p->col->col_wide.cols;
@@ -1226,7 +1231,7 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     ra.partials = (ra.last && nmse) ? w.partials : nullptr;
     ra.theta_next = ra.last ? nullptr : sub_phase + (size_t)(s + 1) * n;
     ca.levels = holograms ? holograms + (size_t)s * n : nullptr;
-    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b, p->col_blocks, ck.threads, ck.lds, ca);
+    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b, p->ospr_col_blocks, ck.ospr_threads, ck.ospr_lds, ca);
     launch(p, HG_KERNEL_OSPR_C, stream, ra.last ? rk.ospr_c : rk.ospr_ca, p->row_blocks, rk.threads, rk.lds, ra);
   }
   if (nmse)
@@ -1275,7 +1280,7 @@ hg_status hg_ospr_pairs(hg_plan p, const float* target_amp, const float* sub_pha
     ra.theta_next = final_pair ? nullptr : sub_phase + (size_t)(s + 1) * n;
     ca.levels = holograms ? holograms + (size_t)(2 * s) * n : nullptr;
     ca.levels_im = holograms ? holograms + (size_t)(2 * s + 1) * n : nullptr;
-    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b_pair, p->col_blocks, ck.threads, ck.lds, ca);
+    launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b_pair, p->ospr_col_blocks, ck.ospr_threads, ck.ospr_lds, ca);
     launch(p, HG_KERNEL_OSPR_C, stream, final_pair ? rk.ospr_c : rk.ospr_ca, p->row_blocks, rk.threads, rk.lds, ra);
   }
   // one partial per block: at most PAIR_MAX_BLOCKS, and never more than the

@@ -1298,10 +1298,10 @@ struct OsprColArgs {
 // the column FFT of the complex field h_re + i h_im carries both (pass C and
 // k_ospr_pair_finish separate their intensities).
 template <int N, bool PAIR>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_ospr_b(OsprColArgs a) {
-  using C = ColCfg<N>;
+__global__ __launch_bounds__(ColCfgOspr<N>::THREADS) void k_ospr_b(OsprColArgs a) {
+  using C = ColCfgOspr<N>;
   using P = typename C::P;
-  using LL = ColLds<N>;
+  using LL = ColLdsOf<C>;
   using LI = Layout<P, true, false>;
   using LF = Layout<P, false, false>;
   using L2 = Layout<P, false, true>;
@@ -1449,6 +1449,8 @@ struct ColKernels {
   void (*as_inv)(AsColArgs);
   int cols, threads;
   size_t lds;
+  int ospr_cols, ospr_threads;   // OSPR's column pass (ColCfgOspr)
+  size_t ospr_lds;
 };
 struct LengthEntry {
   int n;
@@ -1506,7 +1508,8 @@ LengthEntry make_length_entry() {
   e.row.ft = RowTeam<RowCfg<N>>::FT;
   e.col = {k_prop_col<N, -1>, k_prop_col<N, +1>, k_gs_col<N, COL_REPLACE>, k_gs_col<N, COL_NMSE>,
            k_gs_col<N, COL_REPLACE, true>, k_gs_col<N, COL_NMSE, true>, k_gs_col<N, COL_GRAD>, k_ospr_b<N, false>, k_ospr_b<N, true>, k_as_col<N, +1>, k_as_col<N, -1>,
-           ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS};
+           ColCfg<N>::C, ColCfg<N>::THREADS, sizeof(float2) * ColLds<N>::WORDS,
+           ColCfgOspr<N>::C, ColCfgOspr<N>::THREADS, sizeof(float2) * ColLdsOf<ColCfgOspr<N>>::WORDS};
   if constexpr (ColCfgWide<N>::DEFINED) {
     using CW = ColCfgWide<N>;
     e.col_wide = {k_gs_col<N, COL_REPLACE, false, true>, k_gs_col<N, COL_NMSE, false, true>,

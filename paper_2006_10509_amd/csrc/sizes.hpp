@@ -93,7 +93,7 @@ HG_COL_CFG(128,   16,    16,   8, 2, 8)
 HG_COL_CFG(256,    8,    16,   16, 16)
 HG_COL_CFG(512,   8,    64,   8, 8, 8)
 HG_COL_CFG(1024,   2,   128,   8, 4, 4, 8)
-HG_COL_CFG(2048,   4,   128,   16, 8, 16)
+HG_COL_CFG(2048,   2,   128,   16, 8, 16)
 HG_COL_CFG(4096,   1,   512,   8, 8, 8, 8)
 HG_COL_CFG(24,    16,     8,   8, 3)
 HG_COL_CFG(60,    16,    16,   4, 3, 5)
@@ -123,6 +123,26 @@ template <int N> struct ColCfgWide { static constexpr bool DEFINED = false; stat
 // 1024^2 in batches of 8: 10.9 us per hologram-iteration with four columns
 // per workgroup against 11.9 with two (a single hologram: 19.9 against 18.7).
 HG_COL_WIDE(1024, 4)
+
+// Columns per workgroup of OSPR's column pass (binarisation between the two
+// transforms, no error sums), with the teams of ColCfg<N>: ColCfg<N>'s unless
+// specialised.  At 2048 the GS passes are faster with two columns (2048^2 GS
+// 57.3 -> 56.6 us per iteration; a batch of 16 at Fourier L = 4: 32.2 ->
+// 30.5 ms) and OSPR's pass B with four (22.1 -> 16.9 us).
+template <int N> struct ColCfgOspr {
+  using P = typename ColCfg<N>::P;
+  static constexpr int C = ColCfg<N>::C;
+  static constexpr int THREADS = ColCfg<N>::THREADS;
+  static constexpr bool WAVE_SYNC = ColCfg<N>::WAVE_SYNC;
+};
+#define HG_COL_OSPR(N_, C_)                                               \
+  template <> struct ColCfgOspr<N_> {                                    \
+    using P = typename ColCfg<N_>::P;                                    \
+    static constexpr int C = C_;                                         \
+    static constexpr int THREADS = C_ * P::T;                            \
+    static constexpr bool WAVE_SYNC = (C_ * P::T <= 64);                 \
+  };
+HG_COL_OSPR(2048, 4)
 
 // X-macro over every compiled length (used for host dispatch tables).
 #define HG_FOR_EACH_LENGTH(X) \
