@@ -435,11 +435,15 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
     pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, nmse=nm, stream=stream))
     pair_nmse = float(nm.item())
     # per-pass durations of the plain run (every launch executed TIMING_REPEATS
-    # times back to back): pass B moves 17 B/px; pass C, which after the first
-    # subframe also runs the next subframe's pass A, 32 B/px
+    # times back to back).  The hologram is real, so pass B stores only the
+    # rows y <= H/2 of its column transform: it reads 8 B/px, writes the level
+    # (1 B/px) and half the field (4 B/px), 13 B/px.  Pass C, which after the
+    # first subframe also runs the next subframe's pass A, reads that half
+    # (4), reads and writes the intensity (8), reads the target and the next
+    # phase (8) and writes the field (8): 28 B/px
     npx = w.width * w.height
     passes = {}
-    for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 17), ("pass_c", hg.HG_KERNEL_OSPR_C, 32)):
+    for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 13), ("pass_c", hg.HG_KERNEL_OSPR_C, 28)):
         hg.hg_timing_begin(plan, kid, TIMING_REPEATS)
         hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream)
         total_ms, count = hg.hg_timing_end(plan)

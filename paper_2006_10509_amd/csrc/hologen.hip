@@ -93,6 +93,8 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   chk(allow_lds(e->row.ospr_a, e->row.lds));
   chk(allow_lds(e->row.ospr_c, e->row.lds));
   chk(allow_lds(e->row.ospr_ca, e->row.lds));
+  chk(allow_lds(e->row.ospr_c_half, e->row.lds));
+  chk(allow_lds(e->row.ospr_ca_half, e->row.lds));
   chk(allow_lds(e->col.prop_fwd, e->col.lds));
   chk(allow_lds(e->col.prop_inv, e->col.lds));
   chk(allow_lds(e->col.gs_col, e->col.lds));
@@ -181,6 +183,7 @@ struct hg_plan_s {
   bool wide_ok = false;
   int col_blocks_wide = 0;
   int ospr_col_blocks = 0;   // workgroups of OSPR's column pass
+  int ospr_pair_blocks = 0;  // workgroups of OSPR's pass C over row pairs
   // per-column error partials of one state: the padded width of the widest
   // column configuration
   int col_slots = 0;
@@ -1044,6 +1047,7 @@ hg_status hg_plan_create(const hg_plan_desc* desc, hg_plan* out) {
   p->row_blocks = (H + p->row->row.teams - 1) / p->row->row.teams;
   p->col_blocks = (W + p->col->col.cols - 1) / p->col->col.cols;
   p->ospr_col_blocks = (W + p->col->col.ospr_cols - 1) / p->col->col.ospr_cols;
+  p->ospr_pair_blocks = (H / 2 + 1 + p->row->row.teams - 1) / p->row->row.teams;
   // Tiled where the row kernels are compiled for a tile width that the column
   // passes' widths divide (whole-line accesses on both passes); row order
   // elsewhere.
@@ -1232,11 +1236,12 @@ hg_status hg_ospr(hg_plan p, const float* target_amp, const float* sub_phase, in
     ra.theta_next = ra.last ? nullptr : sub_phase + (size_t)(s + 1) * n;
     ca.levels = holograms ? holograms + (size_t)s * n : nullptr;
     launch(p, HG_KERNEL_OSPR_B, stream, ck.ospr_b, p->ospr_col_blocks, ck.ospr_threads, ck.ospr_lds, ca);
-    launch(p, HG_KERNEL_OSPR_C, stream, ra.last ? rk.ospr_c : rk.ospr_ca, p->row_blocks, rk.threads, rk.lds, ra);
+    launch(p, HG_KERNEL_OSPR_C, stream, ra.last ? rk.ospr_c_half : rk.ospr_ca_half, p->ospr_pair_blocks,
+           rk.threads, rk.lds, ra);
   }
   if (nmse)
     hipLaunchKernelGGL(k_nmse_reduce, dim3(1), dim3(STATS_THREADS), 0, stream, (const float*)w.partials,
-                       p->row_blocks, (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
+                       p->ospr_pair_blocks, (const Scalars*)w.sc, nmse, (size_t)0, (size_t)0);
   return launch_status("hg_ospr launch");
 }
 

@@ -1294,9 +1294,12 @@ struct OsprColArgs {
 };
 
 // Pass B: inverse column FFT -> h = sign(Re G) -> level -> forward column FFT of h.
+// The hologram is real, so its column transform is conjugate-symmetric,
+// Z[H-y] = conj Z[y]: only the rows y <= H/2 are stored (pass C's row pairs
+// take the rest from them).
 // PAIR: two subframes from one G, h_re = sign(Re G) and h_im = sign(Im G), and
 // the column FFT of the complex field h_re + i h_im carries both (pass C and
-// k_ospr_pair_finish separate their intensities).
+// k_ospr_pair_finish separate their intensities); all rows are stored.
 template <int N, bool PAIR>
 __global__ __launch_bounds__(ColCfgOspr<N>::THREADS) void k_ospr_b(OsprColArgs a) {
   using C = ColCfgOspr<N>;
@@ -1333,7 +1336,17 @@ __global__ __launch_bounds__(ColCfgOspr<N>::THREADS) void k_ospr_b(OsprColArgs a
     v[s] = make_float2(neg ? -1.0f : 1.0f, im);
   });
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  if (live) for_layout<L2>(t, [&](int s, int y) { stg(a.field, f.at(y), v[s]); });
+  if (live)
+    for_layout<L2>(t, [&](int s, int y) {
+      if (PAIR || y <= N / 2) stg(a.field, f.at(y), v[s]);
+    });
+}
+
+// (N/2 - k) mod N: the centred position of frequency -k of an N-point row.
+template <int NC>
+__device__ __forceinline__ int centred_neg(int k) {
+  const int j = NC / 2 - k;
+  return j < 0 ? j + NC : j;
 }
 
 // Pass C: row FFT -> |.|^2 -> accumulate into the centred intensity (fftshift on
@@ -1343,7 +1356,13 @@ __global__ __launch_bounds__(ColCfgOspr<N>::THREADS) void k_ospr_b(OsprColArgs a
 // passes.  Its phase and the target are loaded after pass C's transform,
 // while the intensity is accumulated (loaded with the field, they held
 // registers through the transform: 4.5 % slower at 2048^2).
-template <int N, bool NEXT>
+// HALF (a real hologram, whose pass B stored the rows y <= H/2): a team takes
+// the row pair (y, H - y), y = 0..H/2.  Row H - y of the 2D transform is
+// F[H-y][k] = conj F[y][-k], so one row transform gives both intensity rows,
+// |F[H-y][k]|^2 = |F[y][-k]|^2 (centred: position (H - r, N - c) mod (H, N)
+// mirrors (r, c)); with NEXT the team then runs pass A of both rows.  Rows 0
+// and H/2 pair with themselves.
+template <int N, bool NEXT, bool HALF>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using C = RowCfg<N>;
   using P = typename C::P;
@@ -1351,45 +1370,82 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using L0 = Layout<P, false, false>;
   using L1 = Layout<P, false, true>;
   __shared__ float red[C::THREADS / 64];
-  const RowTeam<C> rt(a.H, a.ft);
+  const RowTeam<C> rt(HALF ? a.H / 2 + 1 : a.H, a.ft);
   const int t = rt.t;
+  // the mirror row (HALF), and whether it is another row than y
+  const int ym = HALF && rt.y != 0 ? a.H - rt.y : rt.y;
+  const bool two = HALF && ym != rt.y;
+  constexpr int RM = HALF ? P::REGS : 1;
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
   for_layout<L0>(t, [&](int s, int x) { v[s] = ldg(a.field, f.at(x)); });
   const uint32_t orow = (uint32_t)wrap_add_rt(rt.y, a.H / 2, a.H) * N;
+  const uint32_t orow_m = (uint32_t)wrap_add_rt(ym, a.H / 2, a.H) * N;
   const bool nm = !NEXT && a.last && a.partials;
-  float prev[P::REGS], tg[P::REGS];
+  // The mirror row's loads are issued with row y's where registers allow
+  // (at most 8 values per thread, below 1024 threads); elsewhere after the
+  // transform that needs them.
+  constexpr bool EARLY_M = C::THREADS < 1024 && P::REGS <= 8;
+  float prev[P::REGS], tg[P::REGS], prev_m[RM], tg_m[RM];
+  auto load_acc_mirror = [&]() {
+    for_layout<L1>(t, [&](int s, int k) {
+      const uint32_t im = orow_m + centred_neg<N>(k);
+      prev_m[s] = a.first || !two ? 0.0f : ldg(a.intensity, im);
+      tg_m[s] = nm && two ? ldg(a.target, im) : 0.0f;
+    });
+  };
   for_layout<L1>(t, [&](int s, int k) {
     const uint32_t i = orow + wrap_add<N>(k, N / 2);
     prev[s] = a.first ? 0.0f : ldg(a.intensity, i);
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
+  if constexpr (HALF && EARLY_M) load_acc_mirror();
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, false, !NEXT>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if constexpr (TW::USES_LDS) __syncthreads();
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+  if constexpr (HALF && !EARLY_M) load_acc_mirror();
   float th[NEXT ? P::REGS : 1], am[NEXT ? P::REGS : 1];
+  float th_m[NEXT ? RM : 1], am_m[NEXT ? RM : 1];
+  auto load_mirror = [&]() {
+    for_layout<L0>(t, [&](int s, int x) {
+      const uint32_t im = orow_m + wrap_add<N>(x, N / 2);
+      th_m[s] = ldg(a.theta_next, im);
+      am_m[s] = ldg(a.target, im);
+    });
+  };
   if constexpr (NEXT) {
     for_layout<L0>(t, [&](int s, int x) {
       const uint32_t i = orow + wrap_add<N>(x, N / 2);
       th[s] = ldg(a.theta_next, i);
       am[s] = ldg(a.target, i);
     });
+    if constexpr (HALF && EARLY_M) load_mirror();
   }
   float acc = 0.f;
   const float sa = nm ? a.sc->a : 0.f;
   const float sb = nm ? a.sc->b : 0.f;
   for_layout<L1>(t, [&](int s, int k) {
-    float I = cnorm(v[s]) + prev[s];
+    const float e = cnorm(v[s]);
+    float I = e + prev[s];
     if (!NEXT && a.last) {
       I *= a.inv_nsub;
       const float d = fmaf(I, sa, -(tg[s] * tg[s] * sb));
       acc = fmaf(d, d, acc);
     }
     if (rt.live) stg(a.intensity, orow + wrap_add<N>(k, N / 2), I);
+    if constexpr (HALF) {
+      float Im = e + prev_m[s];
+      if (!NEXT && a.last) {
+        Im *= a.inv_nsub;
+        const float d = fmaf(Im, sa, -(tg_m[s] * tg_m[s] * sb));
+        if (two) acc = fmaf(d, d, acc);
+      }
+      if (rt.live && two) stg(a.intensity, orow_m + centred_neg<N>(k), Im);
+    }
   });
   if (a.partials) {
     const float s = block_sum<C::THREADS>(rt.live ? acc : 0.0f, red);
@@ -1403,6 +1459,19 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     });
     tw.template run<false, +1, C::WAVE_SYNC>(v, t, lds);
     if (rt.live) for_layout<L1>(t, [&](int s, int x) { stg(a.field, f.at(x), v[s]); });
+    if constexpr (HALF) {
+      // every team transforms (the exchanges' barriers span the workgroup);
+      // only a distinct mirror row is stored
+      if constexpr (!EARLY_M) load_mirror();
+      for_layout<L0>(t, [&](int s, int) {
+        float sn, cs;
+        sincosf(th_m[s], &sn, &cs);
+        v[s] = make_float2(am_m[s] * cs, am_m[s] * sn);
+      });
+      tw.template run<false, +1, C::WAVE_SYNC>(v, t, lds);
+      const RowField fm = RowField::make<N, RowTeam<C>::FT>(t, ym, a.H, a.ft);
+      if (rt.live && two) for_layout<L1>(t, [&](int s, int x) { stg(a.field, fm.at(x), v[s]); });
+    }
   }
 }
 
@@ -1419,6 +1488,8 @@ struct RowKernels {
   void (*ospr_a)(OsprRowArgs);
   void (*ospr_c)(OsprRowArgs);
   void (*ospr_ca)(OsprRowArgs);   // pass C, then the next subframe's pass A
+  void (*ospr_c_half)(OsprRowArgs);    // the same over row pairs (real holograms)
+  void (*ospr_ca_half)(OsprRowArgs);
   void (*grad_row)(GradRowArgs);
   void (*grad_row_next)(GradRowArgs);   // ... then the next forward row pass
   void (*as_row)(AsRowArgs);
@@ -1496,8 +1567,10 @@ LengthEntry make_length_entry() {
   e.row.gs_row_mp[3] = k_gs_row<N, GS_Q4, false, true>;
   e.row.gs_row_mp[4] = k_gs_row<N, GS_Q8, false, true>;
   e.row.ospr_a = k_ospr_a<N>;
-  e.row.ospr_c = k_ospr_c<N, false>;
-  e.row.ospr_ca = k_ospr_c<N, true>;
+  e.row.ospr_c = k_ospr_c<N, false, false>;
+  e.row.ospr_ca = k_ospr_c<N, true, false>;
+  e.row.ospr_c_half = k_ospr_c<N, false, true>;
+  e.row.ospr_ca_half = k_ospr_c<N, true, true>;
   e.row.grad_row = k_grad_row<N, false>;
   e.row.grad_row_next = k_grad_row<N, true>;
   e.row.as_row = k_as_row<N, true>;
