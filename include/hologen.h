@@ -303,7 +303,9 @@ hg_status hg_pixel_search(hg_plan plan, const float* target_amp, uint8_t* levels
  *         sum I_j = (H W)^2 by Parseval)
  *   dL/dphi = sum_j 2 Im(conj(V_j) F^H(dL/dI_j * U_j)),  F^H = H W IFFT2,
  *   dL/dI_j = 2 (I_j/sum I_j - T_j/sum T_j) / (sum I_j sum (T_j/sum T_j)^2).
- * V_j is recomputed from phi in the adjoint pass, never stored.
+ * V_j is recomputed from phi in the adjoint pass, never stored.  A state
+ * costs two launches whatever n_planes: one column pass over every plane and
+ * one row pass that sums the planes' gradients in registers.
  * planes     [n_planes] plans, 1 <= n_planes <= 16.                 (required)
  * target_amp [n_planes][H][W] float, centred, >= 0, each not all zero.  (required)
  * workspace  hg_grad_workspace_bytes(planes[0], n_planes) bytes.    (required)
@@ -333,10 +335,11 @@ hg_status hg_grad_adam(const hg_plan* planes, int32_t n_planes, const float* tar
  * uses target_amp + b n_planes H W (its n_planes targets), phase, grad,
  * adam_m and adam_v + b H W, and loss + b (hg_grad_batched: one value) or
  * loss + b (steps + 1) (hg_grad_adam_batched); the planes are shared.
- * 1 <= batch <= 65535 and batch H W' < 2^32 (W' = W rounded up to the field's
- * column-tile width).  workspace: hg_grad_workspace_bytes_batched(planes[0],
- * n_planes, batch) bytes (the fields and accumulators of all problems are
- * resident together).  Other arguments and errors as hg_grad / hg_grad_adam. */
+ * 1 <= batch, batch n_planes <= 65535 and batch n_planes H W' < 2^32 (W' = W
+ * rounded up to the field's column-tile width).  workspace:
+ * hg_grad_workspace_bytes_batched(planes[0], n_planes, batch) bytes (one
+ * field per plane of every problem, resident together).  Other arguments and
+ * errors as hg_grad / hg_grad_adam. */
 size_t hg_grad_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch);
 hg_status hg_grad_batched(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
                           const float* phase, float* grad, float* loss, void* workspace, hipStream_t stream);

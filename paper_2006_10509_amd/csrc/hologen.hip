@@ -108,8 +108,7 @@ hipError_t prepare_kernels(const LengthEntry* e) {
   }
   chk(allow_lds(e->col.ospr_b, e->col.ospr_lds));
   chk(allow_lds(e->col.ospr_b_pair, e->col.ospr_lds));
-  chk(allow_lds(e->row.grad_row, e->row.lds));
-  chk(allow_lds(e->row.grad_row_next, e->row.lds));
+  for (auto k : e->row.grad_rows) chk(allow_lds(k, e->row.lds));
   chk(allow_lds(e->col.grad_col, e->col.lds));
   chk(allow_lds(e->row.as_row, e->row.lds));
   chk(allow_lds(e->row.as_row_nmse, e->row.lds));
@@ -422,21 +421,41 @@ ColLaunch col_launch(hg_plan p, int batch) {
 }
 
 // Workspace of the gradient method for `batch` problems of `planes` replay
-// planes each: fields [batch] | dL/dphi accumulators [batch][H][W] | Scalars
-// [batch][planes] | stats | loss partials [batch][kNmseChunk states][planes]
-// [column workgroups] | tiled targets [batch][planes].  batch = 1 is the
-// single-problem layout.
+// planes each: fields [batch][planes] | Scalars [batch][planes] | stats |
+// loss partials [kNmseChunk states][batch][planes][column workgroups] | tiled
+// targets [batch][planes].  batch = 1 is the single-problem layout.  The
+// fields, scalars, partials and targets of (problem b, plane j) are item
+// b planes + j of the column launch over every plane of every problem.
 struct GradLayout {
-  size_t acc, sc, stats, partials, target, target_stride, total;
-  size_t partial_stride;   // floats of loss partials per problem
+  size_t sc, stats, partials, target, target_stride, total;
+  size_t state_stride;     // floats of loss partials per state
 };
 
 GradLayout grad_layout(hg_plan p, int planes, int batch = 1) {
-  const size_t n = npix(p);
   GradLayout g{};
-  g.partial_stride = (size_t)kNmseChunk * planes * p->col_slots;
-  g.acc = align_up((size_t)batch * field_elems(p) * sizeof(float2));
-  g.sc = g.acc + align_up((size_t)batch * n * sizeof(float));
+  g.state_stride = (size_t)batch * planes * p->col_slots;
+  g.sc = align_up((size_t)batch * planes * field_elems(p) * sizeof(float2));
+  g.stats = g.sc + align_up((size_t)batch * planes * sizeof(Scalars));
+  g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
+  g.target = g.partials + align_up((size_t)kNmseChunk * g.state_stride * sizeof(float));
+  g.target_stride = align_up((size_t)p->col_slots * p->desc.height * sizeof(float));
+  g.total = g.target + (size_t)batch * planes * g.target_stride;
+  return g;
+}
+
+// Workspace of multi-plane GS for `batch` problems of `planes` replay planes:
+// fields [batch] | Scalars [batch][planes] | stats | NMSE partials
+// [batch][kNmseChunk steps][column workgroups] | tiled targets
+// [batch][planes].
+struct MpLayout {
+  size_t sc, stats, partials, target, target_stride, total;
+  size_t partial_stride;   // floats of NMSE partials per problem
+};
+
+MpLayout mp_layout(hg_plan p, int planes, int batch = 1) {
+  MpLayout g{};
+  g.partial_stride = (size_t)kNmseChunk * p->col_slots;
+  g.sc = align_up((size_t)batch * field_elems(p) * sizeof(float2));
   g.stats = g.sc + align_up((size_t)batch * planes * sizeof(Scalars));
   g.partials = g.stats + align_up((size_t)STATS_MAX_BLOCKS * 3 * sizeof(double));
   g.target = g.partials + align_up((size_t)batch * g.partial_stride * sizeof(float));
@@ -465,46 +484,38 @@ hg_status validate_planes(const hg_plan* planes, int n_planes) {
 // loss[k] receives the summed NMSE of state k (nullable).
 // `batch` problems side by side (grid.y = problem): problem b uses
 // target_amp + b P H W, phase / grad / m / v + b H W and loss + b loss_stride,
-// and its arithmetic is exactly that of a single-problem call.
+// and its arithmetic is exactly that of a single-problem call.  A state is
+// one column launch over every plane of every problem (item b P + j) and one
+// row pass over every problem that handles all its planes.
 hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_amp, float* phase, float* grad,
                    float* m, float* v, int steps, int first_step, float lr, float beta1, float beta2, float eps,
                    float* loss, size_t loss_stride, bool final_loss, void* workspace, hipStream_t stream) {
   hg_plan p0 = planes[0];
   const int W = p0->desc.width, H = p0->desc.height;
   const size_t n = npix(p0);
+  const int items = batch * P;
   const GradLayout L = grad_layout(p0, P, batch);
   char* ws = static_cast<char*>(workspace);
   float2* field = reinterpret_cast<float2*>(ws);
-  float* acc = reinterpret_cast<float*>(ws + L.acc);
   Scalars* sc = reinterpret_cast<Scalars*>(ws + L.sc);
   double* stats = reinterpret_cast<double*>(ws + L.stats);
   float* partials = reinterpret_cast<float*>(ws + L.partials);
   const RowKernels& rk = p0->row->row;
-  const ColLaunch cl = col_launch(p0, batch);
+  const ColLaunch cl = col_launch(p0, items);
   const int cols = cl.cols;
   const uint32_t tiled_n = (uint32_t)cl.slots() * H;
   const int nb = stats_blocks(n);
-  for (int b = 0; b < batch; ++b)
-    for (int j = 0; j < P; ++j) {
-      const float* tj = target_amp + ((size_t)b * P + j) * n;
-      float* tiled = reinterpret_cast<float*>(ws + L.target + ((size_t)b * P + j) * L.target_stride);
-      hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, tj, tiled, H, W, cols,
-                         tiled_n);
-      hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, tj, (const float*)nullptr, n,
-                         stats);
-      hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
-                         (double)n * (double)n, (double)n, sc + (size_t)b * P + j);
-    }
-  const dim3 rows(p0->row_blocks, batch), tiles(cl.blocks, batch);
-  GsRowArgs fa{};   // forward row pass: continuous phase, no illumination, no outputs
-  fa.ft = p0->ft;
-  fa.field = field;
-  fa.phase0 = phase;
-  fa.H = H;
-  fa.tw = p0->tw_row[0];
-  fa.twr = p0->tw_row[1];
-  fa.px = (uint32_t)n;
-  fa.fpx = (uint32_t)field_elems(p0);
+  for (int i = 0; i < items; ++i) {
+    const float* ti = target_amp + (size_t)i * n;
+    float* tiled = reinterpret_cast<float*>(ws + L.target + (size_t)i * L.target_stride);
+    hipLaunchKernelGGL(k_tile_target, dim3((tiled_n + 255) / 256), dim3(256), 0, stream, ti, tiled, H, W, cols,
+                       tiled_n);
+    hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(STATS_THREADS), 0, stream, ti, (const float*)nullptr, n,
+                       stats);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STATS_THREADS), 0, stream, (const double*)stats, nb, n, 0,
+                       (double)n * (double)n, (double)n, sc + i);
+  }
+  const dim3 rows(p0->row_blocks, batch), tiles(cl.blocks, items);
   GsColArgs ca{};
   ca.ft = p0->ft;
   ca.field = field;
@@ -513,9 +524,11 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
   ca.tw = p0->tw_col[0];
   ca.twr = p0->tw_col[1];
   ca.px = (uint32_t)field_elems(p0);
-  ca.target_stride = (uint32_t)((size_t)P * L.target_stride / sizeof(float));
-  ca.sc_stride = (uint32_t)P;
-  ca.partial_stride = (uint32_t)L.partial_stride;
+  ca.target = reinterpret_cast<const float*>(ws + L.target);
+  ca.target_stride = (uint32_t)(L.target_stride / sizeof(float));
+  ca.sc = sc;
+  ca.sc_stride = 1;
+  ca.partial_stride = (uint32_t)cl.slots();
   GradRowArgs ga{};
   ga.px = (uint32_t)n;
   ga.fpx = (uint32_t)field_elems(p0);
@@ -523,7 +536,12 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
   ga.field = field;
   ga.phase = phase;
   ga.H = H;
-  ga.acc = acc;
+  ga.planes = P;
+  for (int j = 0; j < P; ++j) {
+    const bool fres = planes[j]->desc.propagation == HG_FRESNEL;
+    ga.q1y[j] = fres ? planes[j]->q1y : nullptr;
+    ga.q1x[j] = fres ? planes[j]->q1x : nullptr;
+  }
   ga.grad_out = grad;
   ga.m = m;
   ga.v = v;
@@ -534,55 +552,30 @@ hg_status grad_run(const hg_plan* planes, int P, int batch, const float* target_
   ga.tw = p0->tw_row[0];
   ga.twr = p0->tw_row[1];
   const bool backward = grad || m;
-  auto plane_chirp = [&](int j, const float2*& qy, const float2*& qx) {
-    const bool fres = planes[j]->desc.propagation == HG_FRESNEL;
-    qy = fres ? planes[j]->q1y : nullptr;
-    qx = fres ? planes[j]->q1x : nullptr;
-  };
   const int states = steps + (final_loss ? 1 : 0);
+  hipLaunchKernelGGL(rk.grad_rows[GRAD_START], rows, dim3(rk.threads), rk.lds, stream, ga);
   int chunk0 = 0;
-  // true when the field already holds the forward row pass of the plane about
-  // to be evaluated (made by the previous adjoint row pass)
-  bool started = false;
   for (int k = 0; k < states; ++k) {
     const bool is_step = k < steps;
-    if (is_step && m) {
-      const int t = first_step + k;
-      ga.bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
-      ga.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
-    }
-    for (int j = 0; j < P; ++j) {
-      if (!started) {
-        plane_chirp(j, fa.q1y, fa.q1x);
-        hipLaunchKernelGGL(rk.gs_start, rows, dim3(rk.threads), rk.lds, stream, fa);
+    ca.partials = loss ? partials + (size_t)(k - chunk0) * L.state_stride : nullptr;
+    if (is_step && backward) {
+      if (m) {
+        const int t = first_step + k;
+        ga.bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+        ga.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
       }
-      started = false;
-      ca.target = reinterpret_cast<const float*>(ws + L.target + (size_t)j * L.target_stride);
-      ca.sc = sc + j;
-      ca.partials = loss ? partials + ((size_t)(k - chunk0) * P + j) * cl.slots() : nullptr;
-      if (is_step && backward) {
-        hipLaunchKernelGGL(cl.grad_col, tiles, dim3(cl.threads), cl.lds, stream, ca);
-        plane_chirp(j, ga.q1y, ga.q1x);
-        ga.first = j == 0;
-        ga.last = j == P - 1;
-        // the next evaluation: plane j + 1 of this state, else plane 0 of the
-        // next state (the phase this pass leaves: updated by Adam, or as it was)
-        const int nj = j + 1 < P ? j + 1 : (k + 1 < states ? 0 : -1);
-        if (nj >= 0) {
-          plane_chirp(nj, ga.qny, ga.qnx);
-          hipLaunchKernelGGL(rk.grad_row_next, rows, dim3(rk.threads), rk.lds, stream, ga);
-          started = true;
-        } else {
-          hipLaunchKernelGGL(rk.grad_row, rows, dim3(rk.threads), rk.lds, stream, ga);
-        }
-      } else if (loss) {
-        hipLaunchKernelGGL(cl.gs_col_nmse, tiles, dim3(cl.threads), cl.lds, stream, ca);
-      }
+      hipLaunchKernelGGL(cl.grad_col, tiles, dim3(cl.threads), cl.lds, stream, ca);
+      // the next state's forward evaluation (from the phase this pass leaves)
+      // runs in the same pass when another state follows
+      const int mode = k + 1 < states ? GRAD_ADJ_NEXT : GRAD_ADJ;
+      hipLaunchKernelGGL(rk.grad_rows[mode], rows, dim3(rk.threads), rk.lds, stream, ga);
+    } else if (loss) {
+      hipLaunchKernelGGL(cl.gs_col_nmse, tiles, dim3(cl.threads), cl.lds, stream, ca);
     }
     if (loss && (k - chunk0 == kNmseChunk - 1 || k == states - 1)) {
       hipLaunchKernelGGL(k_loss_reduce, dim3(k - chunk0 + 1, batch), dim3(STATS_THREADS), 0, stream,
                          (const float*)partials, cl.slots(), P, (const Scalars*)sc, loss + chunk0,
-                         L.partial_stride, loss_stride);
+                         (size_t)P * cl.slots(), L.state_stride, loss_stride);
       chunk0 = k + 1;
     }
   }
@@ -814,7 +807,7 @@ hg_status gs_validate(hg_plan p, const float* target_amp, const float* phase, in
 // Multi-plane GS on `batch` same-shape problems (batch 1: hg_gs_multiplane).
 // Problem b takes target_amp + b P N, phase and levels + b N and nmse + b (P
 // iterations + P); its field, Scalars, partial sums and tiled targets lie at
-// the item strides of grad_layout, and every pass is one launch over all
+// the item strides of mp_layout, and every pass is one launch over all
 // problems (gridDim.y), with the wide column configuration where there is one.
 hg_status multiplane_run(const hg_plan* planes, int32_t n_planes, int32_t batch, const float* target_amp,
                          const float* illumination, float* phase, uint8_t* levels, float* nmse, int32_t iterations,
@@ -835,7 +828,7 @@ hg_status multiplane_run(const hg_plan* planes, int32_t n_planes, int32_t batch,
   hg_plan p0 = planes[0];
   const int W = p0->desc.width, H = p0->desc.height;
   const size_t n = npix(p0);
-  const GradLayout L = grad_layout(p0, P, batch);
+  const MpLayout L = mp_layout(p0, P, batch);
   char* ws = static_cast<char*>(workspace);
   float2* field = reinterpret_cast<float2*>(ws);
   Scalars* sc = reinterpret_cast<Scalars*>(ws + L.sc);
@@ -1412,7 +1405,7 @@ size_t hg_multiplane_workspace_bytes(hg_plan plan, int32_t n_planes) {
 
 size_t hg_multiplane_workspace_bytes_batched(hg_plan plan, int32_t n_planes, int32_t batch) {
   if (!plan || n_planes < 1 || n_planes > kMaxPlanes || batch < 1 || batch > 65535) return 0;
-  return grad_layout(plan, n_planes, batch).total;
+  return mp_layout(plan, n_planes, batch).total;
 }
 
 hg_status hg_gs_multiplane(const hg_plan* planes, int32_t n_planes, const float* target_amp,
@@ -1449,8 +1442,9 @@ hg_status grad_validate(const hg_plan* planes, int32_t n_planes, int32_t batch, 
   if (!target_amp) return fail(HG_ERR_INVALID_ARGUMENT, "target_amp is NULL");
   if (!workspace) return fail(HG_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (batch < 1 || batch > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch must be in 1..65535");
-  if ((size_t)batch * field_elems(planes[0]) > (size_t)UINT32_MAX)
-    return fail(HG_ERR_INVALID_ARGUMENT, "batch * height * (padded) width must be below 2^32");
+  if ((size_t)batch * n_planes > 65535) return fail(HG_ERR_INVALID_ARGUMENT, "batch * n_planes must be <= 65535");
+  if ((size_t)batch * n_planes * field_elems(planes[0]) > (size_t)UINT32_MAX)
+    return fail(HG_ERR_INVALID_ARGUMENT, "batch * n_planes * height * (padded) width must be below 2^32");
   return HG_OK;
 }
 

@@ -19,10 +19,12 @@
 //   Propagation (Fourier / single-FFT Fresnel):
 //     k_prop_row, k_prop_col
 //   Gradient-descent hologram (multi-plane NMSE loss, Wirtinger gradient, Adam):
-//     k_gs_row_start  phi -> Q1_j exp(i phi) -> row FFT    (continuous mode)
+//     k_grad_rows     START: phi -> Q1_j exp(i phi) -> row FFT, every plane
 //     k_gs_col        column FFT -> loss partial, dL/dconj(U) -> inverse column FFT
-//     k_grad_row      inverse row FFT -> 2 Im(conj(V_j) G_j) summed over planes
-//                     [-> gradient out] [-> Adam step on phi]
+//                     (one launch over every plane of every problem)
+//     k_grad_rows     ADJ: inverse row FFT -> 2 Im(conj(V_j) G_j) summed over
+//                     the planes in registers [-> gradient out] [-> Adam step
+//                     on phi] [-> START of the next state]
 //
 // Conventions.  The field is row-major [H][W] complex64 (float2).  The forward
 // transform uses exp(-2 pi i ...) and is unnormalised; inverse transforms
@@ -476,6 +478,13 @@ struct RowTableDirect {
     if constexpr (IN_REGS) return r[i];
     else return src[x];
   }
+};
+
+// A per-column table read from global memory where it is used.
+struct RowTableGlobal {
+  const float2* src;
+  __device__ __forceinline__ void begin(const float2* s, int) { src = s; }
+  __device__ __forceinline__ float2 at(int, int x) const { return src[x]; }
 };
 
 // ===========================================================================
@@ -973,127 +982,156 @@ __global__ __launch_bounds__((ColCfgSel<N, WIDE>::THREADS)) void k_gs_col(GsColA
 // ===========================================================================
 // Gradient-descent hologram optimisation: adjoint row pass
 // ===========================================================================
+// Row passes of the gradient method: every plane of one state in one pass, the
+// sum over planes in registers (problem blockIdx.y of a batch).
+constexpr int GRAD_MAX_PLANES = 16;
+enum { GRAD_START = 0, GRAD_ADJ = 1, GRAD_ADJ_NEXT = 2 };
 struct GradRowArgs {
-  float2* field;           // in: output of the COL_GRAD pass of this plane;
-                           // out (NEXT): forward row pass of the next plane
-  int ft;                  // its layout (RowField)
+  float2* field;           // [planes] fields of the problem, fpx elements apart:
+                           // in (ADJ): outputs of the COL_GRAD passes;
+                           // out (START, ADJ_NEXT): forward row passes of the next state
+  int ft;                  // their layout (RowField)
   float* phase;            // SLM phase phi [H][W]; updated in place by the Adam step
   int H;
-  const float2* q1y;       // source chirp of this plane; null -> Fourier plane
-  const float2* q1x;
-  float* acc;              // dL/dphi summed over the planes so far [H][W]
-  int first, last;         // first plane: no accumulator read; last: finish
-  float* grad_out;         // last plane: dL/dphi; may be null
-  float* m;                // last plane: Adam moments [H][W]; null -> no update
+  int planes;
+  const float2* q1y[GRAD_MAX_PLANES];   // source chirp of each plane; null -> Fourier plane
+  const float2* q1x[GRAD_MAX_PLANES];
+  float* grad_out;         // dL/dphi; may be null
+  float* m;                // Adam moments [H][W]; null -> no update
   float* v;
   float lr, beta1, beta2, eps;
   float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
-  const float2* qny;       // NEXT: source chirp of the next plane; null -> Fourier plane
-  const float2* qnx;
   const float2* tw;
   const float2* twr;
   uint32_t px;             // batch: pixels per problem (row-order arrays)
-  uint32_t fpx;            // batch: field elements per problem
-  // Problem blockIdx.y of a launch over a batch of same-shape problems.
-  __device__ __forceinline__ void select_item() {
-    const uint32_t off = blockIdx.y * px;
-    field += blockIdx.y * fpx;
-    phase += off;
-    acc += off;
-    if (grad_out) grad_out += off;
-    if (m) m += off;
-    if (v) v += off;
+  uint32_t fpx;            // field elements per plane
+};
+// The arrays of problem blockIdx.y of a launch over a batch of same-shape
+// problems.  (Kept apart from the arguments: the per-plane chirp pointers
+// are indexed at run time and must stay in the kernel-argument segment.)
+struct GradItem {
+  float2* field;
+  float *phase, *grad_out, *m, *v;
+  __device__ __forceinline__ explicit GradItem(const GradRowArgs& a) {
+    const size_t off = (size_t)blockIdx.y * a.px;
+    field = a.field + (size_t)blockIdx.y * a.planes * a.fpx;
+    phase = a.phase + off;
+    grad_out = a.grad_out ? a.grad_out + off : nullptr;
+    m = a.m ? a.m + off : nullptr;
+    v = a.v ? a.v + off : nullptr;
   }
 };
 
-// Inverse row FFT (completes G = F^H dL/dconj(U) of this plane) -> V = Q1
-// exp(i phi) recomputed from phi rather than stored -> g = 2 Im(conj(V) G)
-// added to the sum over planes; after the last plane the sum is written out
-// and/or one Adam step updates phi.  The accumulator, moments and phase are
-// loaded with the field, before the transform.  NEXT: the same pass then
-// starts the next forward evaluation from the phase it holds (the next plane,
-// or after the last plane the next state's first plane, from the updated
-// phase): Q1' exp(i phi) -> row FFT -> field, the arithmetic of
-// k_gs_row_start on a continuous phase, so the gradient method needs no
-// separate start pass after its first.
-template <int N, bool NEXT>
-__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_row(GradRowArgs a) {
-  a.select_item();
+// ADJ: for each plane j, inverse row FFT (completes G_j = F^H dL/dconj(U_j))
+// -> V_j = Q1_j exp(i phi) recomputed from phi rather than stored -> g +=
+// 2 Im(conj(V_j) G_j), planes in order; then the gradient is written out
+// and/or one Adam step updates phi.  The phase and moments are loaded with
+// the first plane's field; exp(i phi) is formed once for all planes.
+// START, and ADJ_NEXT after the above: the forward evaluation of every plane
+// from the phase held (updated by Adam, or as it was): Q1_j exp(i phi) -> row
+// FFT -> field j (the arithmetic of k_gs_row_start on a continuous phase).
+// A state thus costs one row pass and one column launch over all planes.
+template <int N, int MODE>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_rows(GradRowArgs a) {
+  const GradItem it(a);
   using C = RowCfg<N>;
   using P = typename C::P;
   using LL = RowLds<N>;
   using LI = Layout<P, true, false>;   // first stage of the reversed (inverse) run
   using LF = Layout<P, false, false>;  // its last stage == first of the forward run
   using L1 = Layout<P, false, true>;   // last stage of the forward run
+  constexpr bool ADJ = MODE != GRAD_START;
+  constexpr bool FWD = MODE != GRAD_ADJ;
   const RowTeam<C> rt(a.H, a.ft);
   const int t = rt.t;
+  const bool live = rt.live;
   LdsView<1> lds{hg_dyn_lds + rt.team * LL::TEAM};
   float2 v[P::REGS];
   const uint32_t row = (uint32_t)rt.y * N;
   const RowField f = RowField::make<N, RowTeam<C>::FT>(t, rt.y, a.H, a.ft);
-  for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(a.field, f.at(x)); });
-  float ph[P::REGS], ac[P::REGS], mm[P::REGS], vv[P::REGS];
-  const bool adam = a.last && a.m != nullptr;
-  for_layout<LF>(t, [&](int s, int x) {
-    ph[s] = ldg_f<N>(a.phase, row + x);
-    ac[s] = a.first ? 0.0f : ldg_f<N>(a.acc, row + x);
-    mm[s] = adam ? ldg_f<N>(a.m, row + x) : 0.0f;
-    vv[s] = adam ? ldg_f<N>(a.v, row + x) : 0.0f;
-  });
+  if constexpr (ADJ) for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(it.field, f.at(x)); });
+  float ph[P::REGS], g[ADJ ? P::REGS : 1], mm[ADJ ? P::REGS : 1], vv[ADJ ? P::REGS : 1];
+  const bool adam = ADJ && it.m != nullptr;
+  for_layout<LF>(t, [&](int s, int x) { ph[s] = ldg_f<N>(it.phase, row + x); });
   issue_loads_here();
-  using TW = PassTwiddles<P, C::THREADS, NEXT, true, !NEXT>;
-  using QX = RowTable<N, LF>;
-  using QN = RowTableDirect<N, LF>;
+  using TW = PassTwiddles<P, C::THREADS, FWD, ADJ, false>;
+  // each plane's chirp row table is read where it is used (from L2: every
+  // row of every problem reads the same W values); held in registers it would
+  // add 2 REGS live registers to the plane loops
+  using QT = RowTableGlobal;
   TW tw;
-  QX qx;
-  QN qn;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
-  const bool fres = a.q1y != nullptr;
-  const bool nfres = NEXT && a.qny != nullptr;
-  if (fres) qx.begin(a.q1x, t);
-  if (nfres) qn.begin(a.qnx, t);
-  // this row's chirp values load with the tables (see k_gs_row)
-  const float2 qy = fres ? a.q1y[rt.y] : make_float2(1.f, 0.f);
-  const float2 qny = nfres ? a.qny[rt.y] : make_float2(1.f, 0.f);
-  if constexpr (TW::USES_LDS || QX::USES_LDS) __syncthreads();
-  tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
-  if constexpr (!NEXT) {
-    if (!rt.live) return;   // no barrier follows
-  }
-  const bool live = rt.live;
-  for_layout<LF>(t, [&](int s, int x) {
-    const uint32_t i = row + x;
+  if constexpr (TW::USES_LDS) __syncthreads();
+  float2 e[P::REGS];   // exp(i phi), formed once for every plane
+  for_layout<LF>(t, [&](int s, int) {
     float sn, cs;
     sincosf(ph[s], &sn, &cs);
-    float2 V = make_float2(cs, sn);
-    if (fres) V = cmul(V, cmul(qy, qx.at(s, x)));
-    const float2 G = v[s];
-    const float g = fmaf(2.0f, fmaf(V.x, G.y, -(V.y * G.x)), ac[s]);
-    if (!a.last) {
-      if (live) stg_f<N>(a.acc, i, g);
-    } else {
-      if (a.grad_out && live) stg_f<N>(a.grad_out, i, g);
-      if (adam) {
-        const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g);
-        const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g * g);
-        const float phn = ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps);
-        if (live) {
-          stg_f<N>(a.m, i, m1);
-          stg_f<N>(a.v, i, v1);
-          stg_f<N>(a.phase, i, phn);
-        }
-        if constexpr (NEXT) sincosf(phn, &sn, &cs);
+    e[s] = make_float2(cs, sn);
+  });
+  if constexpr (ADJ) {
+#pragma unroll
+    for (int s = 0; s < P::REGS; ++s) g[s] = 0.0f;
+#pragma unroll 1
+    for (int j = 0; j < a.planes; ++j) {
+      const float2* qy_j = a.q1y[j];
+      QT qx;
+      if (qy_j) qx.begin(a.q1x[j], t);
+      const float2 qy = qy_j ? qy_j[rt.y] : make_float2(1.f, 0.f);
+      tw.template run<true, +1, C::WAVE_SYNC>(v, t, lds);
+      for_layout<LF>(t, [&](int s, int x) {
+        float2 V = e[s];
+        if (qy_j) V = cmul(V, cmul(qy, qx.at(s, x)));
+        const float2 G = v[s];
+        g[s] = fmaf(2.0f, fmaf(V.x, G.y, -(V.y * G.x)), g[s]);
+      });
+      if (j + 1 < a.planes) {
+        const float2* fj = it.field + (size_t)(j + 1) * a.fpx;
+        for_layout<LI>(t, [&](int s, int x) { v[s] = ldg_field<N>(fj, f.at(x)); });
       }
     }
-    if constexpr (NEXT) {
-      float2 h = make_float2(cs, sn);
-      if (nfres) h = cmul(h, cmul(qny, qn.at(s, x)));
-      v[s] = h;
+    // the moments are needed only now (loaded earlier, they would hold
+    // registers through every plane's transform)
+    if (adam)
+      for_layout<LF>(t, [&](int s, int x) {
+        mm[s] = ldg_f<N>(it.m, row + x);
+        vv[s] = ldg_f<N>(it.v, row + x);
+      });
+    for_layout<LF>(t, [&](int s, int x) {
+      const uint32_t i = row + x;
+      if (it.grad_out && live) stg_f<N>(it.grad_out, i, g[s]);
+      if (adam) {
+        const float m1 = fmaf(a.beta1, mm[s], (1.0f - a.beta1) * g[s]);
+        const float v1 = fmaf(a.beta2, vv[s], (1.0f - a.beta2) * g[s] * g[s]);
+        const float phn = ph[s] - a.lr * (m1 / a.bc1) / (sqrtf(v1 / a.bc2) + a.eps);
+        if (live) {
+          stg_f<N>(it.m, i, m1);
+          stg_f<N>(it.v, i, v1);
+          stg_f<N>(it.phase, i, phn);
+        }
+        if constexpr (FWD) {
+          float sn, cs;
+          sincosf(phn, &sn, &cs);
+          e[s] = make_float2(cs, sn);
+        }
+      }
+    });
+  }
+  if constexpr (FWD) {
+#pragma unroll 1
+    for (int j = 0; j < a.planes; ++j) {
+      const float2* qy_j = a.q1y[j];
+      QT qx;
+      if (qy_j) qx.begin(a.q1x[j], t);
+      const float2 qy = qy_j ? qy_j[rt.y] : make_float2(1.f, 0.f);
+      for_layout<LF>(t, [&](int s, int x) {
+        float2 h = e[s];
+        if (qy_j) h = cmul(h, cmul(qy, qx.at(s, x)));
+        v[s] = h;
+      });
+      tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
+      float2* fj = it.field + (size_t)j * a.fpx;
+      if (live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(fj, f.at(x), v[s]); });
     }
-  });
-  if constexpr (NEXT) {
-    tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-    if (live) for_layout<L1>(t, [&](int s, int x) { stg_field<N>(a.field, f.at(x), v[s]); });
   }
 }
 
@@ -1490,8 +1528,7 @@ struct RowKernels {
   void (*ospr_ca)(OsprRowArgs);   // pass C, then the next subframe's pass A
   void (*ospr_c_half)(OsprRowArgs);    // the same over row pairs (real holograms)
   void (*ospr_ca_half)(OsprRowArgs);
-  void (*grad_row)(GradRowArgs);
-  void (*grad_row_next)(GradRowArgs);   // ... then the next forward row pass
+  void (*grad_rows[3])(GradRowArgs);   // [GRAD_START, GRAD_ADJ, GRAD_ADJ_NEXT]
   void (*as_row)(AsRowArgs);
   void (*as_row_nmse)(AsRowArgs);
   int teams, threads;
@@ -1571,8 +1608,9 @@ LengthEntry make_length_entry() {
   e.row.ospr_ca = k_ospr_c<N, true, false>;
   e.row.ospr_c_half = k_ospr_c<N, false, true>;
   e.row.ospr_ca_half = k_ospr_c<N, true, true>;
-  e.row.grad_row = k_grad_row<N, false>;
-  e.row.grad_row_next = k_grad_row<N, true>;
+  e.row.grad_rows[GRAD_START] = k_grad_rows<N, GRAD_START>;
+  e.row.grad_rows[GRAD_ADJ] = k_grad_rows<N, GRAD_ADJ>;
+  e.row.grad_rows[GRAD_ADJ_NEXT] = k_grad_rows<N, GRAD_ADJ_NEXT>;
   e.row.as_row = k_as_row<N, true>;
   e.row.as_row_nmse = k_as_row<N, false>;
   e.row.teams = RowCfg<N>::TEAMS;

@@ -207,21 +207,22 @@ __global__ __launch_bounds__(STATS_THREADS) void k_nmse_reduce_planes(const floa
   if (threadIdx.x == 0) nmse[blockIdx.x] = (float)(s / sc[(first + (int)blockIdx.x) % planes].denom);
 }
 
-// loss[k] = sum_j (sum_wg partials[k][j][wg]) / denom_j: the summed NMSE of the
-// `planes` replay planes of state k, one workgroup per state, fixed order.
-// Batch item blockIdx.y takes its partials, Scalars and losses at the given
-// strides.
+// loss[k] = sum_j (sum_wg partials[k][b][j][wg]) / denom_j: the summed NMSE
+// of the `planes` replay planes of state k of problem b = blockIdx.y, one
+// workgroup per state and problem, fixed order.  The partials of state k
+// start k state_stride floats in, those of problem b b problem_stride floats
+// further; its Scalars and losses lie at the given strides.
 __global__ __launch_bounds__(STATS_THREADS) void k_loss_reduce(const float* __restrict__ partials, int nwg,
                                                                int planes, const Scalars* __restrict__ sc,
-                                                               float* __restrict__ loss, size_t partial_stride,
-                                                               size_t loss_stride) {
+                                                               float* __restrict__ loss, size_t problem_stride,
+                                                               size_t state_stride, size_t loss_stride) {
   __shared__ double red[STATS_THREADS];
-  partials += blockIdx.y * partial_stride;
+  partials += blockIdx.y * problem_stride + blockIdx.x * state_stride;
   sc += blockIdx.y * (size_t)planes;
   loss += blockIdx.y * loss_stride;
   double total = 0.0;
   for (int j = 0; j < planes; ++j) {
-    const float* p = partials + ((size_t)blockIdx.x * planes + j) * nwg;
+    const float* p = partials + (size_t)j * nwg;
     double s = 0.0;
     for (int i = threadIdx.x; i < nwg; i += STATS_THREADS) s += (double)p[i];
     s = block_sum_f64<STATS_THREADS>(s, red);

@@ -37,7 +37,10 @@ def oracle_bands(t, thetas):
     return [np.abs(x.real) < 1e-5 * np.abs(x) for x in g]
 
 
-@pytest.mark.parametrize("h,w,n_sub", [(256, 256, 4), (90, 120, 3), (1080, 1920, 2), (512, 512, 6), (16, 8192, 3)])
+# Shapes include one subframe (pass C without the next pass A) and the
+# 8192-point column pass, whose row pairs (y, H - y) span 4097 rows.
+@pytest.mark.parametrize("h,w,n_sub", [(256, 256, 4), (90, 120, 3), (1080, 1920, 2), (512, 512, 6), (16, 8192, 3),
+                                       (64, 32, 1), (8192, 16, 2)])
 def test_ospr_matches_oracle(h, w, n_sub):
     print(f"ospr {h}x{w} n_sub={n_sub}", flush=True)
     t = wl.target_amplitude(h, w, seed=h + w)
