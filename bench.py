@@ -247,6 +247,33 @@ def grad_batch(hg, wl, torch, stream, problems: int) -> dict:
             "final_loss_mean": float(fin.mean()), "initial_loss_mean": float(losses[:, 0].mean().item())}
 
 
+def grad_batched_only(hg, wl, torch, stream, problems: int, steps: int = 50) -> dict:
+    """The 3-plane gradient workload's batched call alone, `steps` Adam steps
+    of every problem in one hg_grad_adam_batched call, timed twice (profiler
+    runs: one column launch and one row launch per step)."""
+    w = wl.GRAD_3PLANE_1024
+    planes = [hg.Plan(w.width, w.height, hg.HG_FRESNEL, w.wavelength, w.pitch, z, hg.HG_PHASE, 0)
+              for z in w.distances]
+    tb = torch.stack([torch.from_numpy(w.targets(bi)) for bi in range(problems)]).cuda()
+    pb0 = torch.stack([torch.from_numpy(w.phase0(bi)) for bi in range(problems)]).cuda()
+    bws = hg.grad_workspace_batched(planes, problems)
+    loss = torch.empty((problems, steps + 1), dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(2):
+        ph = pb0.clone()
+        m = torch.zeros_like(ph)
+        v = torch.zeros_like(ph)
+        torch.cuda.synchronize()
+        a.record(stream)
+        hg.hg_grad_adam_batched(planes, tb, ph, m, v, steps, bws, lr=w.lr, loss=loss, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return {"workload": w.name, "problems": problems, "steps": steps, "ms": round(ms[-1], 3),
+            "problem_steps_per_s": round(problems * steps / (ms[-1] * 1e-3), 1)}
+
+
 def _mix_inputs(item):
     from paper_2006_10509_amd import workloads as wl
     h, w, seed = item
@@ -579,6 +606,10 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256^2 to 8192^2 size sweep")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the size sweep (for profiler runs), printed as one JSON line")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only the 3-plane gradient workload, all problems in one call (for profiler runs)")
+    ap.add_argument("--ospr-only", action="store_true",
+                    help="only the 2048^2 OSPR workload (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 20 device copies of an 8 MiB buffer (rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -592,7 +623,7 @@ def main() -> int:
     from paper_2006_10509_amd import hologen as hg
     from paper_2006_10509_amd import workloads as wl
 
-    if args.headline_only or args.sweep_only:
+    if args.headline_only or args.sweep_only or args.grad_only or args.ospr_only:
         args.no_grad = args.no_batched = args.no_cpu_baseline = True
     mixed = None
     if not (args.no_batched or args.calibrate_copy):
@@ -613,6 +644,13 @@ def main() -> int:
         return 0
     if args.sweep_only:
         print(json.dumps({"size_sweep": size_sweep(hg, wl, torch, torch.cuda.current_stream())}), flush=True)
+        return 0
+    if args.grad_only:
+        print(json.dumps({"grad_batched": grad_batched_only(hg, wl, torch, torch.cuda.current_stream(),
+                                                            args.grad_problems)}), flush=True)
+        return 0
+    if args.ospr_only:
+        print(json.dumps({"ospr": ospr_2048(hg, wl, torch, torch.cuda.current_stream())}), flush=True)
         return 0
     w = wl.GS_FRESNEL_1024
     target, phi0 = w.inputs()
