@@ -1055,10 +1055,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_grad_rows(GradRowArgs a)
   for_layout<LF>(t, [&](int s, int x) { ph[s] = ldg_f<N>(it.phase, row + x); });
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, FWD, ADJ, false>;
-  // each plane's chirp row table is read where it is used (from L2: every
-  // row of every problem reads the same W values); held in registers it would
-  // add 2 REGS live registers to the plane loops
-  using QT = RowTableGlobal;
+  // Each plane's chirp row table: loaded into registers before the plane's
+  // transform where a thread holds at most 8 values, below 1024 threads
+  // (1024-point rows, 3-plane batch: 27.0 ms per 100 steps against 28.7 read
+  // at the point of use); elsewhere read where it is used (from L2), since
+  // 2 REGS more live registers through the plane loops spill there.
+  using QT = std::conditional_t<(P::REGS <= 8 && C::THREADS < 1024), RowTableDirect<N, LF>, RowTableGlobal>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if constexpr (TW::USES_LDS) __syncthreads();
