@@ -58,6 +58,8 @@ def gpu_loss_grad(planes, targets, phi):
     (1024, 1024, [0.40, 0.45, 0.50]),
     (16, 8192, [0.45, 0.50]),
     (4096, 16, [0.5, None]),
+    # the most planes a call takes, Fresnel and Fourier mixed
+    (128, 128, [0.40, None, 0.42, 0.44, None, 0.46, 0.48, 0.50, None, 0.52, 0.54, 0.56, None, 0.58, 0.60, 0.62]),
 ])
 def test_loss_and_gradient_match_oracle(h, w, distances):
     print(f"grad {h}x{w} planes={distances}", flush=True)
@@ -249,4 +251,9 @@ def test_batched_gradient_rejects_bad_batches():
     arr = (ctypes.c_void_p * 1)(planes[0].handle)
     ws = hg.grad_workspace_batched(planes, 1)
     st = hg.library().hg_grad_batched(arr, 1, 0, t.data_ptr(), p.data_ptr(), None, p.data_ptr(), ws.data_ptr(), None)
+    assert st == hg.HG_ERR_INVALID_ARGUMENT
+    # one column launch takes every plane of every problem: batch * n_planes <= 65535
+    arr16 = (ctypes.c_void_p * 16)(*([planes[0].handle] * 16))
+    st = hg.library().hg_grad_batched(arr16, 16, 4096, t.data_ptr(), p.data_ptr(), None, p.data_ptr(),
+                                      ws.data_ptr(), None)
     assert st == hg.HG_ERR_INVALID_ARGUMENT
