@@ -459,6 +459,24 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
 
     plain_ms = timed(lambda: hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream))
     plain_nmse = float(nm.item())
+    eager_out = (inten.clone(), nm.clone())
+    # the plain call captured once into a HIP graph and replayed (its inputs
+    # are unchanged by a call, so every replay must equal the eager call)
+    inten_g = torch.empty_like(inten)
+    nm_g = torch.empty_like(nm)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            hg.hg_ospr(plan, t, th, inten_g, ws, nmse=nm_g)
+    stream.wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_same = torch.equal(inten_g, eager_out[0]) and torch.equal(nm_g, eager_out[1])
+    graph_ms = timed(lambda: graph.replay())
+    graph_same = graph_same and torch.equal(inten_g, eager_out[0]) and torch.equal(nm_g, eager_out[1])
     pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, nmse=nm, stream=stream))
     pair_nmse = float(nm.item())
     # per-pass durations of the plain run (every launch executed TIMING_REPEATS
@@ -480,6 +498,8 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return {"workload": w.name, "subframes": w.subframes, "plain_ms": round(plain_ms, 3),
             "plain_subframes_per_s": round(w.subframes / (plain_ms * 1e-3), 1), "plain_nmse": plain_nmse,
+            "plain_graph": {"ms": round(graph_ms, 3), "subframes_per_s": round(w.subframes / (graph_ms * 1e-3), 1),
+                            "bitwise_equal_to_eager": graph_same},
             "pairs_ms": round(pair_ms, 3), "pairs_subframes_per_s": round(w.subframes / (pair_ms * 1e-3), 1),
             "pairs_nmse": pair_nmse, "passes": passes}
 
@@ -510,6 +530,31 @@ def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
     b.record(stream)
     b.synchronize()
     ms = a.elapsed_time(b)
+    eager_out = (lev.clone(), acc.clone(), nm.clone())
+    # the same call captured once into a HIP graph (its 1000 launches), replayed
+    # from the same starting level map; every replay must equal the eager call
+    lev_g = lev0.clone()
+    acc_g = torch.empty_like(acc)
+    nm_g = torch.empty_like(nm)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            hg.hg_pixel_search(plan, t, lev_g, trials, ws, accepted=acc_g, nmse=nm_g)
+    stream.wait_stream(side)
+    graph_ms, graph_same = [], True
+    for _ in range(3):
+        lev_g.copy_(lev0)
+        torch.cuda.synchronize()
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        b.synchronize()
+        graph_ms.append(a.elapsed_time(b))
+        graph_same = graph_same and all(torch.equal(x, y) for x, y in zip((lev_g, acc_g, nm_g), eager_out))
+    g_ms = min(graph_ms)
     rate = float(acc.float().mean().item())
     # one pass over R per two trials: it reads R and T^2 and writes R back when
     # either trial of the previous pair was accepted
@@ -523,7 +568,9 @@ def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
             "trials_per_s": round(n_trials / (ms * 1e-3), 1), "us_per_trial": round(ms * 1e3 / n_trials, 2),
             "trials_per_launch": 2, "us_per_launch": round(us_launch, 2),
             "accept_rate": round(rate, 4), "nmse_start": float(nm[0].item()), "nmse_end": float(nm[-1].item()),
-            "pass_gbs": round(gbs, 1), "pass_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "pass_gbs": round(gbs, 1), "pass_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "graph": {"ms": round(g_ms, 2), "trials_per_s": round(n_trials / (g_ms * 1e-3), 1),
+                      "us_per_launch": round(g_ms * 1e3 / launches, 2), "bitwise_equal_to_eager": graph_same}}
 
 
 SWEEP_SIZES = (256, 512, 1024, 2048, 4096, 8192)
