@@ -1025,8 +1025,9 @@ struct GradItem {
 // ADJ: for each plane j, inverse row FFT (completes G_j = F^H dL/dconj(U_j))
 // -> V_j = Q1_j exp(i phi) recomputed from phi rather than stored -> g +=
 // 2 Im(conj(V_j) G_j), planes in order; then the gradient is written out
-// and/or one Adam step updates phi.  The phase and moments are loaded with
-// the first plane's field; exp(i phi) is formed once for all planes.
+// and/or one Adam step updates phi.  The phase is loaded with the first
+// plane's field and exp(i phi) formed once for all planes; the moments are
+// loaded after the last plane's transform.
 // START, and ADJ_NEXT after the above: the forward evaluation of every plane
 // from the phase held (updated by Adam, or as it was): Q1_j exp(i phi) -> row
 // FFT -> field j (the arithmetic of k_gs_row_start on a continuous phase).
