@@ -561,7 +561,10 @@ def pixel_search_1024(hg, wl, torch, stream, n_trials: int = 2000) -> dict:
     launches = (n_trials + 1) // 2
     pairs_written = float(acc[: n_trials // 2 * 2].view(-1, 2).amax(dim=1).float().mean().item())
     npx = w.height * w.width
-    pass_bytes = npx * (8 + 4 + 8 * pairs_written)
+    # (a binary Fourier hologram is real: the pass keeps the rows y <= H/2 of
+    # R, reads T^2 at every pixel and its mirror)
+    kept = (w.height // 2 + 1) * w.width
+    pass_bytes = kept * (8 + 8 * pairs_written) + npx * 4
     us_launch = ms * 1e3 / launches
     gbs = pass_bytes / (us_launch * 1e-6) / 1e9
     return {"workload": "dbs_fourier_binary_1024x1024", "trials": n_trials, "ms": round(ms, 2),

@@ -1389,11 +1389,19 @@ hg_status hg_pixel_search(hg_plan p, const float* target_amp, uint8_t* levels, c
   sa.wmask = (W & (W - 1)) == 0 ? (uint32_t)(W - 1) : 0u;
   sa.wshift = sa.wmask ? (uint32_t)__builtin_ctz((unsigned)W) : 0u;
   sa.L = p->levels;
-  const int nb = (int)std::min<size_t>((n + SEARCH_THREADS * 4 - 1) / (SEARCH_THREADS * 4), SEARCH_MAX_BLOCKS);
-  hipLaunchKernelGGL(k_search_error, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa);
+  // A binary hologram on a Fourier plane is real (levels +-1), so R is
+  // conjugate-symmetric and the search keeps the rows y <= H/2 of it.
+  const bool half = p->desc.propagation == HG_FOURIER && p->levels == 2 && H % 2 == 0;
+  sa.hh = half ? H / 2 + 1 : H;
+  const size_t n_kept = (size_t)sa.hh * W;
+  const int nb =
+      (int)std::min<size_t>((n_kept + SEARCH_THREADS * 4 - 1) / (SEARCH_THREADS * 4), SEARCH_MAX_BLOCKS);
+  hipLaunchKernelGGL(half ? k_search_error<true> : k_search_error<false>, dim3(nb), dim3(SEARCH_THREADS), 0, stream,
+                     sa);
   hipLaunchKernelGGL(k_search_start, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, nb);
   for (int k = 0; k < n_trials; k += 2)
-    hipLaunchKernelGGL(k_search_step, dim3(nb), dim3(SEARCH_THREADS), 0, stream, sa, k, (int)n_trials);
+    hipLaunchKernelGGL(half ? k_search_step<true> : k_search_step<false>, dim3(nb), dim3(SEARCH_THREADS), 0, stream,
+                       sa, k, (int)n_trials);
   if (n_trials > 0)
     hipLaunchKernelGGL(k_search_finish, dim3(1), dim3(SEARCH_THREADS), 0, stream, sa, n_trials, nb);
   return launch_status("hg_pixel_search launch");

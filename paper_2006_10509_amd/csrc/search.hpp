@@ -77,6 +77,10 @@ struct SearchArgs {
   uint8_t* accepted;           // [n] or null
   float* nmse;                 // [n + 1] or null
   int H, W;
+  // rows of R the search keeps and updates: H/2 + 1 when the hologram is real
+  // (binary levels, Fourier plane: R(-u) = conj R(u), so the rows y <= H/2
+  // hold all of R), else H
+  int hh;
   uint32_t hmask, wmask;       // H - 1, W - 1 for a power of two, else 0
   uint32_t wshift;             // log2 W when wmask is set
   int L;                       // number of levels
@@ -115,15 +119,34 @@ __global__ __launch_bounds__(256) void k_search_phase(const uint8_t* __restrict_
     phase[i] = (float)levels[i] * delta;
 }
 
+// HALF (a.hh < a.H): pixel (uy, ux) of a kept row 0 < uy < H/2 stands for
+// itself and its mirror (H - uy, -ux mod W), which has the same |R| and the
+// same change of |R|^2 under any move; rows 0 and H/2 hold their own mirrors.
+// The mirror's T^2 index, or -1 when the pixel has no separate mirror.
+template <bool HALF>
+__device__ __forceinline__ int search_mirror(const SearchArgs& a, uint32_t uy, uint32_t ux) {
+  if (!HALF || uy == 0 || 2 * uy == (uint32_t)a.H) return -1;
+  return (int)(((uint32_t)a.H - uy) * (uint32_t)a.W + (ux == 0 ? 0u : (uint32_t)a.W - ux));
+}
+
 // Sum of d^2 over R (FP64), one partial per workgroup.
+template <bool HALF>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_search_error(SearchArgs a) {
   __shared__ double red[SEARCH_THREADS];
-  const size_t n = (size_t)a.H * a.W;
+  const size_t n = (size_t)a.hh * a.W;
   const float sa = a.sc->a, sb = a.sc->b;
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * SEARCH_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * SEARCH_THREADS) {
-    const float d = fmaf(cnorm(a.replay[i]), sa, -(a.t2[i] * sb));
+    const float nr = cnorm(a.replay[i]);
+    const float d = fmaf(nr, sa, -(a.t2[i] * sb));
     acc += (double)d * d;
+    if constexpr (HALF) {
+      const int im = search_mirror<HALF>(a, (uint32_t)(i / a.W), (uint32_t)(i % a.W));
+      if (im >= 0) {
+        const float dm = fmaf(nr, sa, -(a.t2[im] * sb));
+        acc += (double)dm * dm;
+      }
+    }
   }
   acc = block_sum_f64<SEARCH_THREADS>(acc, red);
   if (threadIdx.x == 0) a.partials[blockIdx.x] = acc;
@@ -258,16 +281,24 @@ __device__ __forceinline__ double search_de(float2 r, float2 dr, float c2, float
   const float s = sa * fmaf(2.0f, fmaf(r.x, dr.x, r.y * dr.y), c2);
   return (double)s * (double)fmaf(2.0f, d, s);
 }
+// The same with the pixel's mirror (error dm), whose change conj(dr) of
+// conj(r) gives the same s: s (2 d + s) + s (2 dm + s).
+__device__ __forceinline__ double search_de_pair(float2 r, float2 dr, float c2, float d, float dm, float sa) {
+  const float s = sa * fmaf(2.0f, fmaf(r.x, dr.x, r.y * dr.y), c2);
+  return (double)s * (double)fmaf(2.0f, d, s) + (double)s * (double)fmaf(2.0f, dm, s);
+}
 
 // Trials k and k + 1 (k + 1 < n, else trial k alone): decide the previous
 // launch's pending trials, apply the accepted moves to R, sum this
 // workgroup's parts of dE of trial k and of trial k + 1 in both contexts.
+// HALF: the pass runs over the kept rows only (search_mirror).
+template <bool HALF>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_search_step(SearchArgs a, int k, int n) {
   __shared__ double red[3 * SEARCH_THREADS];
   const int buf = (k >> 1) & 1;
   const SearchState st = a.state[buf];
   const int nb = (int)gridDim.x;
-  const uint32_t npx = (uint32_t)a.H * (uint32_t)a.W;
+  const uint32_t npx = (uint32_t)a.hh * (uint32_t)a.W;
   const uint32_t i0 = blockIdx.x * SEARCH_THREADS + threadIdx.x, stride = gridDim.x * SEARCH_THREADS;
   // This thread's first elements of R and T^2 do not depend on the pending
   // decisions: their loads go out before the decisions, whose partial-sum
@@ -349,6 +380,22 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search_step(SearchArgs a, in
     const float t2 = t2raw * sb;
     const float d = fmaf(cnorm(r), sa, -t2);
     const float2 dr0 = cmul(m0.c, search_wave(a, uy, m0, one_col ? x0 : search_wave_x(a, ux, m0)));
+    if constexpr (HALF) {
+      const int im = search_mirror<HALF>(a, uy, ux);
+      if (im >= 0) {
+        const float t2m = a.t2[im] * sb;
+        const float dm = fmaf(cnorm(r), sa, -t2m);
+        acc0 += search_de_pair(r, dr0, c0, d, dm, sa);
+        if (two) {
+          const float2 w1 = search_wave(a, uy, m1r, one_col ? x1 : search_wave_x(a, ux, m1r));
+          acc1r += search_de_pair(r, cmul(m1r.c, w1), c1r, d, dm, sa);
+          const float2 ra = cadd(r, dr0);
+          const float na = cnorm(ra);
+          acc1a += search_de_pair(ra, cmul(m1a.c, w1), c1a, fmaf(na, sa, -t2), fmaf(na, sa, -t2m), sa);
+        }
+        continue;
+      }
+    }
     acc0 += search_de(r, dr0, c0, d, sa);
     if (two) {
       const float2 w1 = search_wave(a, uy, m1r, one_col ? x1 : search_wave_x(a, ux, m1r));

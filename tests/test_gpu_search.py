@@ -58,10 +58,15 @@ def make_trials(h, w, levels, n, seed):
     return np.stack([rng.integers(0, h * w, n), rng.integers(0, levels, n)], axis=1), rng
 
 
+# Binary Fourier cases run the conjugate-symmetric half of R (rows y <= H/2,
+# each pixel with its mirror): square, non-power-of-two and wide frames.
 @pytest.mark.parametrize("h,w,levels,fresnel,n", [
     (32, 32, 2, False, 400),
+    (90, 120, 2, False, 300),
+    (16, 512, 2, False, 201),
     (24, 60, 4, True, 301),
     (64, 64, 8, True, 200),
+    (32, 32, 2, True, 300),
 ])
 def test_direct_search_matches_oracle(h, w, levels, fresnel, n):
     print(f"search {h}x{w} L={levels} fresnel={fresnel} trials={n}", flush=True)
