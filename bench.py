@@ -484,11 +484,12 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
     # rows y <= H/2 of its column transform: it reads 8 B/px, writes the level
     # (1 B/px) and half the field (4 B/px), 13 B/px.  Pass C, which after the
     # first subframe also runs the next subframe's pass A, reads that half
-    # (4), reads and writes the intensity (8), reads the target and the next
-    # phase (8) and writes the field (8): 28 B/px
+    # (4), reads and writes the running intensity of the same rows (the
+    # intensity is centro-symmetric; 2 + 2), reads the target and the next
+    # phase (8) and writes the field (8): 24 B/px
     npx = w.width * w.height
     passes = {}
-    for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 13), ("pass_c", hg.HG_KERNEL_OSPR_C, 28)):
+    for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 13), ("pass_c", hg.HG_KERNEL_OSPR_C, 24)):
         hg.hg_timing_begin(plan, kid, TIMING_REPEATS)
         hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream)
         total_ms, count = hg.hg_timing_end(plan)

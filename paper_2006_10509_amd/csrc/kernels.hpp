@@ -1402,7 +1402,8 @@ __device__ __forceinline__ int centred_neg(int k) {
 // F[H-y][k] = conj F[y][-k], so one row transform gives both intensity rows,
 // |F[H-y][k]|^2 = |F[y][-k]|^2 (centred: position (H - r, N - c) mod (H, N)
 // mirrors (r, c)); with NEXT the team then runs pass A of both rows.  Rows 0
-// and H/2 pair with themselves.
+// and H/2 pair with themselves.  The running intensity is kept for row y
+// only; the last subframe (not NEXT) writes the mirror row too.
 template <int N, bool NEXT, bool HALF>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   using C = RowCfg<N>;
@@ -1426,14 +1427,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
   const bool nm = !NEXT && a.last && a.partials;
   // The mirror row's loads are issued with row y's where registers allow
   // (at most 8 values per thread, below 1024 threads); elsewhere after the
-  // transform that needs them.
+  // transform that needs them.  The mirror row's running intensity is never
+  // read: it equals row y's bitwise (the same additions in the same order
+  // from zero), so only the last subframe writes it, from row y's.
   constexpr bool EARLY_M = C::THREADS < 1024 && P::REGS <= 8;
-  float prev[P::REGS], tg[P::REGS], prev_m[RM], tg_m[RM];
+  float prev[P::REGS], tg[P::REGS], tg_m[RM];
   auto load_acc_mirror = [&]() {
     for_layout<L1>(t, [&](int s, int k) {
-      const uint32_t im = orow_m + centred_neg<N>(k);
-      prev_m[s] = a.first || !two ? 0.0f : ldg(a.intensity, im);
-      tg_m[s] = nm && two ? ldg(a.target, im) : 0.0f;
+      tg_m[s] = nm && two ? ldg(a.target, orow_m + centred_neg<N>(k)) : 0.0f;
     });
   };
   for_layout<L1>(t, [&](int s, int k) {
@@ -1441,14 +1442,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
     prev[s] = a.first ? 0.0f : ldg(a.intensity, i);
     tg[s] = nm ? ldg(a.target, i) : 0.0f;
   });
-  if constexpr (HALF && EARLY_M) load_acc_mirror();
+  if constexpr (HALF && !NEXT && EARLY_M) load_acc_mirror();
   issue_loads_here();
   using TW = PassTwiddles<P, C::THREADS, true, false, !NEXT>;
   TW tw;
   tw.begin(a.tw, a.twr, hg_dyn_lds + LL::TWF, t);
   if constexpr (TW::USES_LDS) __syncthreads();
   tw.template run<false, -1, C::WAVE_SYNC>(v, t, lds);
-  if constexpr (HALF && !EARLY_M) load_acc_mirror();
+  if constexpr (HALF && !NEXT && !EARLY_M) load_acc_mirror();
   float th[NEXT ? P::REGS : 1], am[NEXT ? P::REGS : 1];
   float th_m[NEXT ? RM : 1], am_m[NEXT ? RM : 1];
   auto load_mirror = [&]() {
@@ -1478,14 +1479,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_ospr_c(OsprRowArgs a) {
       acc = fmaf(d, d, acc);
     }
     if (rt.live) stg(a.intensity, orow + wrap_add<N>(k, N / 2), I);
-    if constexpr (HALF) {
-      float Im = e + prev_m[s];
-      if (!NEXT && a.last) {
-        Im *= a.inv_nsub;
-        const float d = fmaf(Im, sa, -(tg_m[s] * tg_m[s] * sb));
+    if constexpr (HALF && !NEXT) {
+      if (a.last) {
+        const float d = fmaf(I, sa, -(tg_m[s] * tg_m[s] * sb));
         if (two) acc = fmaf(d, d, acc);
       }
-      if (rt.live && two) stg(a.intensity, orow_m + centred_neg<N>(k), Im);
+      if (rt.live && two) stg(a.intensity, orow_m + centred_neg<N>(k), I);
     }
   });
   if (a.partials) {
