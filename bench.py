@@ -445,6 +445,8 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
     ws = plan.workspace()
     inten = torch.empty((w.height, w.width), dtype=torch.float32, device="cuda")
     nm = torch.empty(1, dtype=torch.float32, device="cuda")
+    # every call writes its binary holograms (level maps) too
+    holo = torch.empty((w.subframes, w.height, w.width), dtype=torch.uint8, device="cuda")
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def timed(f):
@@ -457,27 +459,29 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
         b.synchronize()
         return a.elapsed_time(b) / 5
 
-    plain_ms = timed(lambda: hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream))
+    plain_ms = timed(lambda: hg.hg_ospr(plan, t, th, inten, ws, holograms=holo, nmse=nm, stream=stream))
     plain_nmse = float(nm.item())
-    eager_out = (inten.clone(), nm.clone())
+    eager_out = (inten.clone(), nm.clone(), holo.clone())
     # the plain call captured once into a HIP graph and replayed (its inputs
     # are unchanged by a call, so every replay must equal the eager call)
     inten_g = torch.empty_like(inten)
     nm_g = torch.empty_like(nm)
+    holo_g = torch.empty_like(holo)
     graph = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(stream)
     with torch.cuda.stream(side):
         torch.cuda.synchronize()
         with torch.cuda.graph(graph, stream=side):
-            hg.hg_ospr(plan, t, th, inten_g, ws, nmse=nm_g)
+            hg.hg_ospr(plan, t, th, inten_g, ws, holograms=holo_g, nmse=nm_g)
     stream.wait_stream(side)
     graph.replay()
     torch.cuda.synchronize()
-    graph_same = torch.equal(inten_g, eager_out[0]) and torch.equal(nm_g, eager_out[1])
+    graph_same = all(torch.equal(x, y) for x, y in zip((inten_g, nm_g, holo_g), eager_out))
     graph_ms = timed(lambda: graph.replay())
-    graph_same = graph_same and torch.equal(inten_g, eager_out[0]) and torch.equal(nm_g, eager_out[1])
-    pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, nmse=nm, stream=stream))
+    graph_same = graph_same and all(torch.equal(x, y) for x, y in zip((inten_g, nm_g, holo_g), eager_out))
+    pair_ms = timed(lambda: hg.hg_ospr_pairs(plan, t, th[:w.subframes // 2], inten, ws, holograms=holo, nmse=nm,
+                                             stream=stream))
     pair_nmse = float(nm.item())
     # per-pass durations of the plain run (every launch executed TIMING_REPEATS
     # times back to back).  The hologram is real, so pass B stores only the
@@ -491,7 +495,7 @@ def ospr_2048(hg, wl, torch, stream) -> dict:
     passes = {}
     for name, kid, bpp in (("pass_b", hg.HG_KERNEL_OSPR_B, 13), ("pass_c", hg.HG_KERNEL_OSPR_C, 24)):
         hg.hg_timing_begin(plan, kid, TIMING_REPEATS)
-        hg.hg_ospr(plan, t, th, inten, ws, nmse=nm, stream=stream)
+        hg.hg_ospr(plan, t, th, inten, ws, holograms=holo, nmse=nm, stream=stream)
         total_ms, count = hg.hg_timing_end(plan)
         us = total_ms * 1e3 / count
         gbs = bpp * npx / (us * 1e-6) / 1e9
